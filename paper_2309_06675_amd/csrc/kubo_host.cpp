@@ -1,0 +1,599 @@
+// kubo_host.cpp -- the C ABI of include/kubo.h: validation, planning, workspace
+// layout and the launch sequence.  No device arithmetic happens here.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <new>
+#include <set>
+#include <tuple>
+#include <vector>
+
+#include "../../include/kubo.h"
+#include "kubo_internal.h"
+#include "kubo_launch.h"
+
+using namespace kubo;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Padded size classes with an instantiated forward kernel, and their default
+// workgroup sizes.
+struct ClassInfo {
+    int np;
+    int nt;
+};
+const ClassInfo kClasses[] = {{8, 64}, {16, 128}, {32, 256}};
+constexpr int kNumClasses = sizeof(kClasses) / sizeof(kClasses[0]);
+
+int class_of(int n) {
+    for (int c = 0; c < kNumClasses; ++c)
+        if (n <= kClasses[c].np) return c;
+    return -1;
+}
+
+struct ClassRange {
+    int begin = 0, count = 0;
+};
+
+struct Chunk {
+    int pencil_begin = 0, pencil_count = 0;
+    ClassRange cls[kNumClasses];
+    long long cls_kpts[kNumClasses] = {0};
+    size_t tbytes = 0, pbytes = 0;
+};
+
+struct GraphKey {
+    const void* p[6];
+    double d[2];
+    void* stream;
+    bool operator==(const GraphKey& o) const {
+        return std::memcmp(p, o.p, sizeof(p)) == 0 && d[0] == o.d[0] && d[1] == o.d[1] &&
+               stream == o.stream;
+    }
+};
+
+struct CachedGraph {
+    bool valid = false;
+    GraphKey key{};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+size_t chunk_cap_bytes() {
+    const char* e = std::getenv("KUBO_CHUNK_MB");
+    long mb = e ? std::atol(e) : 512;
+    if (mb < 1) mb = 1;
+    return (size_t)mb << 20;
+}
+
+}  // namespace
+
+struct kubo_plan_s {
+    uint32_t flags = 0;
+    int n_models = 0, nF = 0;
+    long long total_k = 0;
+    std::vector<ModelDev> models;
+    std::vector<int> r0val, grp_start, grp_r, grp_R1, grp_R2, negr;
+    std::vector<PencilItem> pencils;
+    std::vector<BlockItem> blocks;
+    std::vector<Chunk> chunks;
+    int n_slots = 0;
+    long long t_elems = 0;  // complex elements of t (all models)
+    // workspace layout
+    size_t off_tables = 0, off_tp = 0, off_tbuf = 0, off_pbuf = 0, off_partial = 0, total = 0;
+    std::vector<unsigned char> blob;
+    size_t tab_off[9] = {0};
+    const void* uploaded_ws = nullptr;
+    CachedGraph graph_fwd;
+    int max_groups = 2048;
+    // KUBO_F_TIMING: event pairs around per-k kernel launches
+    struct TimeRec {
+        int which;
+        long long kpts;
+        hipEvent_t start, stop;
+    };
+    std::vector<TimeRec> trec;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> tpool;
+    bool capturing = false;
+};
+
+namespace {
+
+Tables device_tables(const kubo_plan_s* p, unsigned char* ws) {
+    unsigned char* b = ws + p->off_tables;
+    Tables t;
+    t.models = reinterpret_cast<const ModelDev*>(b + p->tab_off[0]);
+    t.r0val = reinterpret_cast<const int*>(b + p->tab_off[1]);
+    t.grp_start = reinterpret_cast<const int*>(b + p->tab_off[2]);
+    t.grp_r = reinterpret_cast<const int*>(b + p->tab_off[3]);
+    t.grp_R1 = reinterpret_cast<const int*>(b + p->tab_off[4]);
+    t.grp_R2 = reinterpret_cast<const int*>(b + p->tab_off[5]);
+    t.negr = reinterpret_cast<const int*>(b + p->tab_off[6]);
+    t.pencils = reinterpret_cast<const PencilItem*>(b + p->tab_off[7]);
+    t.blocks = reinterpret_cast<const BlockItem*>(b + p->tab_off[8]);
+    return t;
+}
+
+template <class T>
+void append_blob(std::vector<unsigned char>& blob, size_t& off, const std::vector<T>& v) {
+    off = align_up(blob.size());
+    blob.resize(off + std::max<size_t>(v.size() * sizeof(T), 1));
+    if (!v.empty()) std::memcpy(blob.data() + off, v.data(), v.size() * sizeof(T));
+}
+
+kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_models, int nF,
+                       uint32_t flags, const kubo_tile* tiles, int n_tiles) {
+    P->flags = flags;
+    P->n_models = n_models;
+    P->nF = nF;
+    std::map<int, kubo_tile> tile_of;
+    for (int i = 0; i < n_tiles; ++i) tile_of[tiles[i].n_orb] = tiles[i];
+    const size_t cap = chunk_cap_bytes();
+
+    long long t_off = 0;
+    int slot = 0;
+    // per model: tables and its pencils / blocks (in model order)
+    struct PB {
+        PencilItem pi;
+        std::vector<BlockItem> blocks;
+        size_t tbytes, pbytes;
+        int cls;
+    };
+    std::vector<PB> all;
+    for (int m = 0; m < n_models; ++m) {
+        const kubo_model_desc& d = models[m];
+        ModelDev md{};
+        md.n = d.n_orb;
+        md.nR = d.n_R;
+        md.N0 = d.grid[0];
+        md.N1 = d.grid[1];
+        md.N2 = d.grid[2];
+        md.t_off = t_off;
+        md.Nk = (long long)d.grid[0] * d.grid[1] * d.grid[2];
+        md.f_off = m * nF;
+        // distinct R_x values, ascending, and R grouped by them
+        std::vector<int> xs;
+        for (int r = 0; r < d.n_R; ++r) xs.push_back(d.R[3 * r]);
+        std::sort(xs.begin(), xs.end());
+        xs.erase(std::unique(xs.begin(), xs.end()), xs.end());
+        md.nR0 = (int)xs.size();
+        md.r0_first = (int)P->r0val.size();
+        for (int x : xs) P->r0val.push_back(x);
+        md.gs_first = (int)P->grp_start.size();
+        md.grp_first = (int)P->grp_r.size();
+        int acc = 0;
+        for (int x : xs) {
+            P->grp_start.push_back(acc);
+            for (int r = 0; r < d.n_R; ++r)
+                if (d.R[3 * r] == x) {
+                    P->grp_r.push_back(r);
+                    P->grp_R1.push_back(d.R[3 * r + 1]);
+                    P->grp_R2.push_back(d.R[3 * r + 2]);
+                    ++acc;
+                }
+        }
+        P->grp_start.push_back(acc);
+        md.neg_first = (int)P->negr.size();
+        std::map<std::tuple<int, int, int>, int> idx;
+        for (int r = 0; r < d.n_R; ++r) idx[{d.R[3 * r], d.R[3 * r + 1], d.R[3 * r + 2]}] = r;
+        for (int r = 0; r < d.n_R; ++r)
+            P->negr.push_back(idx[{-d.R[3 * r], -d.R[3 * r + 1], -d.R[3 * r + 2]}]);
+
+        // slab -> pencils -> blocks
+        const long long kb = d.k_begin;
+        const long long kc = d.k_count < 0 ? md.Nk - kb : d.k_count;
+        const long long ke = kb + kc;
+        int kblock = std::min(d.grid[0], 32);
+        auto ti = tile_of.find(d.n_orb);
+        if (ti != tile_of.end()) kblock = std::min(d.grid[0], ti->second.k_block);
+        const int cls = class_of(d.n_orb);
+        md.slot_first = slot;
+        const long long nn = (long long)d.n_orb * d.n_orb;
+        const size_t mat_bytes = (size_t)2 * md.nR0 * nn * 16;
+        if (kc > 0) {
+            for (long long pc = kb / d.grid[0]; pc <= (ke - 1) / d.grid[0]; ++pc) {
+                PB pb;
+                pb.pi.model = m;
+                pb.pi.i1 = (int)(pc % d.grid[1]);
+                pb.pi.i2 = (int)(pc / d.grid[1]);
+                pb.pi.pad = 0;
+                pb.pi.tbuf_off = 0;
+                pb.tbytes = mat_bytes;
+                pb.cls = cls;
+                long long a0 = std::max(kb - pc * d.grid[0], 0LL);
+                long long a1 = std::min(ke - pc * d.grid[0], (long long)d.grid[0]);
+                for (long long a = a0; a < a1; a += kblock) {
+                    BlockItem bi{};
+                    bi.model = m;
+                    bi.i0 = (int)a;
+                    bi.count = (int)std::min<long long>(kblock, a1 - a);
+                    bi.slot = slot++;
+                    bi.i1 = pb.pi.i1;
+                    bi.i2 = pb.pi.i2;
+                    pb.blocks.push_back(bi);
+                }
+                pb.pbytes = mat_bytes * pb.blocks.size();
+                all.push_back(std::move(pb));
+            }
+        }
+        md.slot_count = slot - md.slot_first;
+        P->total_k += kc;
+        P->models.push_back(md);
+        t_off += (long long)d.n_R * nn;
+    }
+    P->t_elems = t_off;
+    P->n_slots = slot;
+
+    // chunks: consecutive pencils while the T and P regions stay under the cap
+    size_t max_t = 0, max_p = 0;
+    Chunk cur;
+    std::vector<std::vector<BlockItem>> cls_blocks(kNumClasses);
+    auto flush = [&]() {
+        if (cur.pencil_count == 0) return;
+        for (int c = 0; c < kNumClasses; ++c) {
+            cur.cls[c].begin = (int)P->blocks.size();
+            cur.cls[c].count = (int)cls_blocks[c].size();
+            cur.cls_kpts[c] = 0;
+            for (auto& b : cls_blocks[c]) {
+                P->blocks.push_back(b);
+                cur.cls_kpts[c] += b.count;
+            }
+            cls_blocks[c].clear();
+        }
+        max_t = std::max(max_t, cur.tbytes);
+        max_p = std::max(max_p, cur.pbytes);
+        P->chunks.push_back(cur);
+        cur = Chunk();
+        cur.pencil_begin = (int)P->pencils.size();
+    };
+    cur.pencil_begin = 0;
+    for (auto& pb : all) {
+        if (cur.pencil_count > 0 && (cur.tbytes + pb.tbytes > cap || cur.pbytes + pb.pbytes > cap))
+            flush();
+        PencilItem pi = pb.pi;
+        pi.tbuf_off = (long long)(cur.tbytes / 16);
+        long long poff = (long long)(cur.pbytes / 16);
+        const long long mat = (long long)(pb.tbytes / 16);
+        for (auto& b : pb.blocks) {
+            b.tbuf_off = pi.tbuf_off;
+            b.pbuf_off = poff;
+            poff += mat;
+            cls_blocks[pb.cls].push_back(b);
+        }
+        P->pencils.push_back(pi);
+        cur.pencil_count++;
+        cur.tbytes += pb.tbytes;
+        cur.pbytes += pb.pbytes;
+    }
+    flush();
+
+    // index tables, uploaded into the workspace on first use
+    append_blob(P->blob, P->tab_off[0], P->models);
+    append_blob(P->blob, P->tab_off[1], P->r0val);
+    append_blob(P->blob, P->tab_off[2], P->grp_start);
+    append_blob(P->blob, P->tab_off[3], P->grp_r);
+    append_blob(P->blob, P->tab_off[4], P->grp_R1);
+    append_blob(P->blob, P->tab_off[5], P->grp_R2);
+    append_blob(P->blob, P->tab_off[6], P->negr);
+    append_blob(P->blob, P->tab_off[7], P->pencils);
+    append_blob(P->blob, P->tab_off[8], P->blocks);
+
+    size_t off = kAlign;  // status word
+    P->off_tables = off;
+    off = align_up(off + P->blob.size());
+    P->off_tp = off;
+    off = align_up(off + (size_t)P->t_elems * 16);
+    P->off_tbuf = off;
+    off = align_up(off + max_t);
+    P->off_pbuf = off;
+    off = align_up(off + max_p);
+    P->off_partial = off;
+    off = align_up(off + (size_t)P->n_slots * nF * 8);
+    P->total = off;
+    return KUBO_OK;
+}
+
+kubo_status validate(const kubo_model_desc* models, int n_models, int nF, uint32_t flags,
+                     const kubo_tile* tiles, int n_tiles) {
+    if (!models || n_models < 1) return KUBO_E_INVALID;
+    if (nF < 1 || nF > kMaxFermi) return KUBO_E_INVALID;
+    if (flags & ~(KUBO_F_GRAPH | KUBO_F_TIMING | KUBO_F_DEBUG_SWEEPCAP)) return KUBO_E_INVALID;
+    if (n_tiles < 0 || (n_tiles > 0 && !tiles)) return KUBO_E_INVALID;
+    for (int i = 0; i < n_tiles; ++i) {
+        const kubo_tile& t = tiles[i];
+        if (t.n_orb < 1 || t.n_orb > kMaxOrb || t.k_block < 1 || t.reserved != 0)
+            return KUBO_E_INVALID;
+        if (t.threads != 0 && t.threads != 64 && t.threads != 128 && t.threads != 256 &&
+            t.threads != 512)
+            return KUBO_E_INVALID;
+    }
+    bool unsupported = false;
+    for (int m = 0; m < n_models; ++m) {
+        const kubo_model_desc& d = models[m];
+        if (d.n_orb < 1 || d.n_R < 1 || !d.R) return KUBO_E_INVALID;
+        for (int a = 0; a < 3; ++a)
+            if (d.grid[a] < 1 || d.grid[a] > (1 << 20)) return KUBO_E_INVALID;
+        const long long Nk = (long long)d.grid[0] * d.grid[1] * d.grid[2];
+        if (d.k_begin < 0 || d.k_begin >= Nk) return KUBO_E_INVALID;
+        if (d.k_count < -1 || d.k_count == 0) return KUBO_E_INVALID;
+        if (d.k_count > 0 && d.k_begin + d.k_count > Nk) return KUBO_E_INVALID;
+        std::set<std::tuple<int, int, int>> seen;
+        std::set<int> xs;
+        for (int r = 0; r < d.n_R; ++r) {
+            auto key = std::make_tuple(d.R[3 * r], d.R[3 * r + 1], d.R[3 * r + 2]);
+            if (!seen.insert(key).second) return KUBO_E_INVALID;
+            xs.insert(d.R[3 * r]);
+            for (int a = 0; a < 3; ++a)
+                if (d.R[3 * r + a] == INT32_MIN) return KUBO_E_INVALID;
+        }
+        for (int r = 0; r < d.n_R; ++r)
+            if (!seen.count(std::make_tuple(-d.R[3 * r], -d.R[3 * r + 1], -d.R[3 * r + 2])))
+                return KUBO_E_INVALID;
+        if (d.n_orb > kMaxOrb) unsupported = true;
+        else if (class_of(d.n_orb) < 0) unsupported = true;
+        if (xs.size() > 16) unsupported = true;
+    }
+    return unsupported ? KUBO_E_UNSUPPORTED : KUBO_OK;
+}
+
+#define HIP_TRY(x)                                  \
+    do {                                            \
+        if ((x) != hipSuccess) return KUBO_E_HIP;   \
+    } while (0)
+
+kubo_status ensure_tables(kubo_plan_s* P, void* ws, hipStream_t s) {
+    if (P->uploaded_ws == ws) return KUBO_OK;
+    HIP_TRY(hipMemcpyAsync(static_cast<unsigned char*>(ws) + P->off_tables, P->blob.data(),
+                           P->blob.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    P->uploaded_ws = ws;
+    return KUBO_OK;
+}
+
+// Event pair around one per-k launch (only outside graph capture).
+struct TimedScope {
+    kubo_plan_s* P;
+    hipStream_t s;
+    bool on = false;
+    kubo_plan_s::TimeRec rec{};
+    TimedScope(kubo_plan_s* P_, hipStream_t s_, int which, long long kpts) : P(P_), s(s_) {
+        if (!(P->flags & KUBO_F_TIMING) || P->capturing) return;
+        if (P->tpool.empty()) {
+            hipEvent_t a, b;
+            if (hipEventCreate(&a) != hipSuccess) return;
+            if (hipEventCreate(&b) != hipSuccess) {
+                (void)hipEventDestroy(a);
+                return;
+            }
+            P->tpool.push_back({a, b});
+        }
+        rec.which = which;
+        rec.kpts = kpts;
+        rec.start = P->tpool.back().first;
+        rec.stop = P->tpool.back().second;
+        P->tpool.pop_back();
+        on = hipEventRecord(rec.start, s) == hipSuccess;
+        if (!on) P->tpool.push_back({rec.start, rec.stop});
+    }
+    void finish() {
+        if (!on) return;
+        if (hipEventRecord(rec.stop, s) == hipSuccess)
+            P->trec.push_back(rec);
+        else
+            P->tpool.push_back({rec.start, rec.stop});
+        on = false;
+    }
+};
+
+kubo_status enqueue_forward(kubo_plan_s* P, const double* t, const double* ef, double eta,
+                            double kT, double* sigma, unsigned char* ws, hipStream_t s) {
+    const Tables tb = device_tables(P, ws);
+    unsigned* status = reinterpret_cast<unsigned*>(ws);
+    double* tp = reinterpret_cast<double*>(ws + P->off_tp);
+    double* tbuf = reinterpret_cast<double*>(ws + P->off_tbuf);
+    double* partial = reinterpret_cast<double*>(ws + P->off_partial);
+    HIP_TRY(launch_clear(status, s));
+    HIP_TRY(launch_hermproj(tb, P->n_models, P->t_elems, t, tp, s));
+    for (const Chunk& c : P->chunks) {
+        HIP_TRY(launch_pencil(tb, c.pencil_begin, c.pencil_count, tp, tbuf, s));
+        for (int k = 0; k < kNumClasses; ++k) {
+            if (c.cls[k].count == 0) continue;
+            FwdLaunch L;
+            L.tb = tb;
+            L.tbuf = tbuf;
+            L.e_fermi = ef;
+            L.partial = partial;
+            L.status = status;
+            L.eta = eta;
+            L.kT = kT;
+            L.nF = P->nF;
+            L.max_sweeps = (P->flags & KUBO_F_DEBUG_SWEEPCAP) ? 1 : kMaxSweeps;
+            L.item_begin = c.cls[k].begin;
+            L.item_count = c.cls[k].count;
+            L.np = kClasses[k].np;
+            L.max_groups = P->max_groups;
+            TimedScope ts(P, s, 0, c.cls_kpts[k]);
+            HIP_TRY(launch_forward(L, s));
+            ts.finish();
+        }
+    }
+    HIP_TRY(launch_reduce(tb, P->n_models, P->nF, partial, sigma, status, s));
+    return KUBO_OK;
+}
+
+bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
+
+}  // namespace
+
+extern "C" {
+
+kubo_status kubo_plan(kubo_plan_t* plan, const kubo_model_desc* models, int32_t n_models,
+                      int32_t n_fermi, uint32_t flags, const kubo_tile* tiles, int32_t n_tiles,
+                      size_t* workspace_bytes) {
+    if (!plan || !workspace_bytes) return KUBO_E_INVALID;
+    kubo_status st = validate(models, n_models, n_fermi, flags, tiles, n_tiles);
+    if (st != KUBO_OK) return st;
+    kubo_plan_s* P = new (std::nothrow) kubo_plan_s();
+    if (!P) return KUBO_E_INVALID;
+    st = build_plan(P, models, n_models, n_fermi, flags, tiles, n_tiles);
+    if (st != KUBO_OK) {
+        delete P;
+        return st;
+    }
+    *plan = P;
+    *workspace_bytes = P->total;
+    return KUBO_OK;
+}
+
+kubo_status kubo_ahc(kubo_plan_t plan, const double* t, const double* e_fermi, double eta,
+                     double kT, double* sigma, void* workspace, size_t workspace_bytes,
+                     void* stream) {
+    if (!plan || !t || !e_fermi || !sigma) return KUBO_E_INVALID;
+    if (!finite_nonneg(eta) || !finite_nonneg(kT)) return KUBO_E_INVALID;
+    if (!workspace || workspace_bytes < plan->total) return KUBO_E_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    unsigned char* ws = static_cast<unsigned char*>(workspace);
+    kubo_status st = ensure_tables(plan, workspace, s);
+    if (st != KUBO_OK) return st;
+    if ((plan->flags & KUBO_F_GRAPH) && s != nullptr) {
+        GraphKey key{};
+        key.p[0] = t;
+        key.p[1] = e_fermi;
+        key.p[2] = sigma;
+        key.p[3] = workspace;
+        key.d[0] = eta;
+        key.d[1] = kT;
+        key.stream = stream;
+        CachedGraph& g = plan->graph_fwd;
+        if (!(g.valid && g.key == key)) {
+            if (g.exec) (void)hipGraphExecDestroy(g.exec);
+            if (g.graph) (void)hipGraphDestroy(g.graph);
+            g = CachedGraph();
+            HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            plan->capturing = true;
+            st = enqueue_forward(plan, t, e_fermi, eta, kT, sigma, ws, s);
+            plan->capturing = false;
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamEndCapture(s, &graph);
+            if (st != KUBO_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return st;
+            }
+            if (e != hipSuccess) return KUBO_E_HIP;
+            hipGraphExec_t exec = nullptr;
+            if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+                (void)hipGraphDestroy(graph);
+                return KUBO_E_HIP;
+            }
+            g.graph = graph;
+            g.exec = exec;
+            g.key = key;
+            g.valid = true;
+        }
+        HIP_TRY(hipGraphLaunch(g.exec, s));
+        return KUBO_OK;
+    }
+    return enqueue_forward(plan, t, e_fermi, eta, kT, sigma, ws, s);
+}
+
+kubo_status kubo_ahc_backward(kubo_plan_t plan, const double* t, const double* e_fermi,
+                              double eta, double kT, const double* sigma_bar, double* grad_t,
+                              void* workspace, size_t workspace_bytes, void* stream) {
+    if (!plan || !t || !e_fermi || !sigma_bar || !grad_t) return KUBO_E_INVALID;
+    if (!finite_nonneg(eta) || !finite_nonneg(kT) || !(eta > 0.0)) return KUBO_E_INVALID;
+    if (!workspace || workspace_bytes < plan->total) return KUBO_E_WORKSPACE;
+    (void)stream;
+    return KUBO_E_UNSUPPORTED;
+}
+
+kubo_status kubo_plan_device_status(kubo_plan_t plan, const void* workspace, void* stream) {
+    if (!plan || !workspace || plan->uploaded_ws != workspace) return KUBO_E_INVALID;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (hipStreamSynchronize(s) != hipSuccess) return KUBO_E_HIP;
+    unsigned v = 0;
+    if (hipMemcpy(&v, workspace, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess) return KUBO_E_HIP;
+    if (v & kStatNoConv) return KUBO_E_NOCONV;
+    if (v & kStatNonFinite) return KUBO_E_NONFINITE;
+    return KUBO_OK;
+}
+
+kubo_status kubo_plan_kernel_time(kubo_plan_t plan, int32_t which, double* total_ms,
+                                  int64_t* launches, int64_t* k_points, int32_t reset) {
+    if (!plan || which < 0 || which > 1) return KUBO_E_INVALID;
+    double ms = 0.0;
+    long long nl = 0, kp = 0;
+    for (const auto& r : plan->trec) {
+        if (r.which != which) continue;
+        if (hipEventSynchronize(r.stop) != hipSuccess) return KUBO_E_HIP;
+        float e = 0.f;
+        if (hipEventElapsedTime(&e, r.start, r.stop) != hipSuccess) return KUBO_E_HIP;
+        ms += e;
+        ++nl;
+        kp += r.kpts;
+    }
+    if (total_ms) *total_ms = ms;
+    if (launches) *launches = nl;
+    if (k_points) *k_points = kp;
+    if (reset) {
+        std::vector<kubo_plan_s::TimeRec> keep;
+        for (const auto& r : plan->trec) {
+            if (r.which == which)
+                plan->tpool.push_back({r.start, r.stop});
+            else
+                keep.push_back(r);
+        }
+        plan->trec.swap(keep);
+    }
+    return KUBO_OK;
+}
+
+void kubo_plan_destroy(kubo_plan_t plan) {
+    if (!plan) return;
+    for (const auto& r : plan->trec) {
+        (void)hipEventDestroy(r.start);
+        (void)hipEventDestroy(r.stop);
+    }
+    for (const auto& e : plan->tpool) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    if (plan->graph_fwd.exec) (void)hipGraphExecDestroy(plan->graph_fwd.exec);
+    if (plan->graph_fwd.graph) (void)hipGraphDestroy(plan->graph_fwd.graph);
+    delete plan;
+}
+
+const char* kubo_status_string(kubo_status status) {
+    switch (status) {
+        case KUBO_OK:
+            return "KUBO_OK";
+        case KUBO_E_INVALID:
+            return "KUBO_E_INVALID: argument out of range";
+        case KUBO_E_UNSUPPORTED:
+            return "KUBO_E_UNSUPPORTED: valid but not implemented";
+        case KUBO_E_WORKSPACE:
+            return "KUBO_E_WORKSPACE: workspace missing or too small";
+        case KUBO_E_HIP:
+            return "KUBO_E_HIP: HIP runtime call failed";
+        case KUBO_E_NOCONV:
+            return "KUBO_E_NOCONV: eigensolver hit its sweep cap";
+        case KUBO_E_NONFINITE:
+            return "KUBO_E_NONFINITE: non-finite value in the result";
+    }
+    return "unknown kubo_status";
+}
+
+kubo_status kubo_plan_info(kubo_plan_t plan, int64_t* total_k_points, int32_t* n_models) {
+    if (!plan) return KUBO_E_INVALID;
+    if (total_k_points) *total_k_points = plan->total_k;
+    if (n_models) *n_models = plan->n_models;
+    return KUBO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,34 @@
+// kubo_launch.h -- host-callable launchers of the device kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kubo_internal.h"
+
+namespace kubo {
+
+struct FwdLaunch {
+    Tables tb;
+    const double* tbuf;
+    const double* e_fermi;
+    double* partial;
+    unsigned* status;
+    double eta, kT;
+    int nF;
+    int max_sweeps;
+    int item_begin, item_count;
+    int np;          // padded size class of every item in the list
+    int max_groups;  // persistent grid size cap
+};
+
+hipError_t launch_clear(unsigned* status, hipStream_t s);
+hipError_t launch_zero(double* p, long long count, hipStream_t s);
+hipError_t launch_hermproj(const Tables& tb, int n_models, long long total, const double* t,
+                           double* tp, hipStream_t s);
+hipError_t launch_pencil(const Tables& tb, int item_begin, int item_count, const double* tp,
+                         double* tbuf, hipStream_t s);
+hipError_t launch_forward(const FwdLaunch& L, hipStream_t s);
+hipError_t launch_reduce(const Tables& tb, int n_models, int nF, const double* partial,
+                         double* sigma, unsigned* status, hipStream_t s);
+
+}  // namespace kubo
