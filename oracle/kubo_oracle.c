@@ -354,17 +354,20 @@ int oracle_bands_k(int n, int nR, const int* R, const double* t, const double* k
 /* sigma_xy[j] for every Fermi level, over the k-slab [k_begin, k_begin+k_count)
  * of the flat grid index, normalised by the FULL grid N_k so that disjoint
  * slabs add up.  sabs[j] (may be NULL) receives (1/N_k) sum of the absolute
- * pair terms, the scale against which cancellation is judged.  nthreads <= 0
+ * pair terms, and sband[j] (may be NULL) (1/N_k) sum_k sum_n f_j(E_n)|Omega_n|,
+ * the magnitude of the terms of the band form -(1/N_k) sum f Omega; they are
+ * the scales against which rounding after cancellation is judged.  nthreads <= 0
  * uses the OpenMP default.  Returns 0, or -1 if some eigensolve did not
  * converge.  The k-sum is Neumaier-compensated in fixed chunks, so the result
  * does not depend on the thread count. */
 int oracle_ahc(int n, int nR, const int* R, const double* t, const int* grid, long k_begin,
                long k_count, int nF, const double* EF, double eta, double kT, double* sigma,
-               double* sabs, int nthreads) {
+               double* sabs, double* sband, int nthreads) {
     long Nk = (long)grid[0] * grid[1] * grid[2];
     long nchunk = (k_count + ORACLE_KCHUNK - 1) / ORACLE_KCHUNK;
     double* csum = calloc((size_t)nchunk * nF, sizeof(double));
     double* cabsum = calloc((size_t)nchunk * nF, sizeof(double));
+    double* cband = calloc((size_t)nchunk * nF, sizeof(double));
     int bad = 0;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -380,11 +383,14 @@ int oracle_ahc(int n, int nR, const int* R, const double* t, const int* grid, lo
         double* fo = malloc((size_t)n * nF * sizeof(double));
         nsum* acc = malloc((size_t)nF * sizeof(nsum));
         nsum* aab = malloc((size_t)nF * sizeof(nsum));
+        nsum* abd = malloc((size_t)nF * sizeof(nsum));
+        double* om = malloc((size_t)n * sizeof(double));
 #pragma omp for schedule(dynamic, 1)
         for (long c = 0; c < nchunk; ++c) {
             for (int j = 0; j < nF; ++j) {
                 acc[j].s = acc[j].c = 0.0;
                 aab[j].s = aab[j].c = 0.0;
+                abd[j].s = abd[j].c = 0.0;
             }
             long kb = k_begin + c * ORACLE_KCHUNK;
             long ke = kb + ORACLE_KCHUNK;
@@ -410,10 +416,24 @@ int oracle_ahc(int n, int nR, const int* R, const double* t, const int* grid, lo
                             nadd(&aab[j], fabs(term));
                         }
                     }
+                if (sband) {
+                    for (int a = 0; a < n; ++a) {
+                        double o = 0.0;
+                        for (int b = 0; b < n; ++b) {
+                            double de = E[a] - E[b];
+                            if (b == a || (eta == 0.0 && de == 0.0)) continue;
+                            o += cimag(A[a * n + b] * B[b * n + a]) * bcast_g(de, eta);
+                        }
+                        om[a] = fabs(2.0 * o);
+                    }
+                    for (int j = 0; j < nF; ++j)
+                        for (int a = 0; a < n; ++a) nadd(&abd[j], fo[a * nF + j] * om[a]);
+                }
             }
             for (int j = 0; j < nF; ++j) {
                 csum[c * nF + j] = nval(&acc[j]);
                 cabsum[c * nF + j] = nval(&aab[j]);
+                cband[c * nF + j] = nval(&abd[j]);
             }
         }
         free(phase);
@@ -424,18 +444,23 @@ int oracle_ahc(int n, int nR, const int* R, const double* t, const int* grid, lo
         free(fo);
         free(acc);
         free(aab);
+        free(abd);
+        free(om);
     }
     for (int j = 0; j < nF; ++j) {
-        nsum s = {0.0, 0.0}, sa = {0.0, 0.0};
+        nsum s = {0.0, 0.0}, sa = {0.0, 0.0}, sb = {0.0, 0.0};
         for (long c = 0; c < nchunk; ++c) {
             nadd(&s, csum[c * nF + j]);
             nadd(&sa, cabsum[c * nF + j]);
+            nadd(&sb, cband[c * nF + j]);
         }
         sigma[j] = nval(&s) / (double)Nk;
         if (sabs) sabs[j] = nval(&sa) / (double)Nk;
+        if (sband) sband[j] = nval(&sb) / (double)Nk;
     }
     free(csum);
     free(cabsum);
+    free(cband);
     return bad ? -1 : 0;
 }
 

@@ -53,7 +53,7 @@ def lib():
                                      _dp, _dp]
         L.oracle_ahc.argtypes = [ctypes.c_int, ctypes.c_int, _ip, _dp, _ip, ctypes.c_long,
                                  ctypes.c_long, ctypes.c_int, _dp, ctypes.c_double,
-                                 ctypes.c_double, _dp, _dp, ctypes.c_int]
+                                 ctypes.c_double, _dp, _dp, _dp, ctypes.c_int]
         L.oracle_band_range.argtypes = [ctypes.c_int, ctypes.c_int, _ip, _dp, _ip, _dp, _dp,
                                         ctypes.c_int]
         L.oracle_ahc_grad.argtypes = [ctypes.c_int, ctypes.c_int, _ip, _dp, _ip, ctypes.c_long,
@@ -115,7 +115,10 @@ def bands_k(t, R, k, eta):
 
 
 def ahc(t, R, grid, e_fermi, eta, kT, k_begin=0, k_count=None, nthreads=0, with_sabs=False):
-    """sigma_xy[j] over a k-slab, normalised by the full grid (Eq. (2)-(3))."""
+    """sigma_xy[j] over a k-slab, normalised by the full grid (Eq. (2)-(3)).
+
+    with_sabs: also return the rounding scale max(S_pair, S_band) per level, where
+    S_pair = (1/N_k) sum |pair terms| and S_band = (1/N_k) sum_k sum_n f_n |Omega_n|."""
     t, R, n, nR = _model(t, R)
     grid = _c(grid, np.int32)
     Nk = int(np.prod(grid.astype(np.int64)))
@@ -125,12 +128,14 @@ def ahc(t, R, grid, e_fermi, eta, kT, k_begin=0, k_count=None, nthreads=0, with_
     nF = EF.size
     sig = np.zeros(nF)
     sabs = np.zeros(nF)
+    sband = np.zeros(nF)
     rc = lib().oracle_ahc(n, nR, _ptr(R, _ip), _ptr(t, _dp), _ptr(grid, _ip), int(k_begin),
                           int(k_count), nF, _ptr(EF, _dp), float(eta), float(kT), _ptr(sig, _dp),
-                          _ptr(sabs, _dp), int(nthreads))
+                          _ptr(sabs, _dp), _ptr(sband, _dp) if with_sabs else None,
+                          int(nthreads))
     if rc != 0:
         raise RuntimeError("oracle eigensolver did not converge")
-    return (sig, sabs) if with_sabs else sig
+    return (sig, np.maximum(sabs, sband)) if with_sabs else sig
 
 
 def band_range(t, R, grid, nthreads=0):
