@@ -44,6 +44,7 @@ struct ClassRange {
 
 struct Chunk {
     int pencil_begin = 0, pencil_count = 0;
+    int grange_begin = 0, grange_count = 0;
     ClassRange cls[kNumClasses];
     long long cls_kpts[kNumClasses] = {0};
     size_t tbytes = 0, pbytes = 0;
@@ -80,7 +81,10 @@ struct kubo_plan_s {
     int n_models = 0, nF = 0;
     long long total_k = 0;
     std::vector<ModelDev> models;
-    std::vector<int> r0val, grp_start, grp_r, grp_R1, grp_R2, negr;
+    std::vector<int> r0val, grp_start, grp_r, grp_R1, grp_R2, grp_rho, negr;
+    std::vector<GaccRange> granges;
+    int max_nR = 0;
+    long long max_nn = 0;
     std::vector<PencilItem> pencils;
     std::vector<BlockItem> blocks;
     std::vector<Chunk> chunks;
@@ -89,9 +93,9 @@ struct kubo_plan_s {
     // workspace layout
     size_t off_tables = 0, off_tp = 0, off_tbuf = 0, off_pbuf = 0, off_partial = 0, total = 0;
     std::vector<unsigned char> blob;
-    size_t tab_off[9] = {0};
+    size_t tab_off[11] = {0};
     const void* uploaded_ws = nullptr;
-    CachedGraph graph_fwd;
+    CachedGraph graph_fwd, graph_bwd;
     int max_groups = 2048;
     // KUBO_F_TIMING: event pairs around per-k kernel launches
     struct TimeRec {
@@ -118,6 +122,8 @@ Tables device_tables(const kubo_plan_s* p, unsigned char* ws) {
     t.negr = reinterpret_cast<const int*>(b + p->tab_off[6]);
     t.pencils = reinterpret_cast<const PencilItem*>(b + p->tab_off[7]);
     t.blocks = reinterpret_cast<const BlockItem*>(b + p->tab_off[8]);
+    t.grp_rho = reinterpret_cast<const int*>(b + p->tab_off[9]);
+    t.granges = reinterpret_cast<const GaccRange*>(b + p->tab_off[10]);
     return t;
 }
 
@@ -169,16 +175,19 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
         md.gs_first = (int)P->grp_start.size();
         md.grp_first = (int)P->grp_r.size();
         int acc = 0;
-        for (int x : xs) {
+        for (int xi = 0; xi < (int)xs.size(); ++xi) {
             P->grp_start.push_back(acc);
             for (int r = 0; r < d.n_R; ++r)
-                if (d.R[3 * r] == x) {
+                if (d.R[3 * r] == xs[xi]) {
                     P->grp_r.push_back(r);
                     P->grp_R1.push_back(d.R[3 * r + 1]);
                     P->grp_R2.push_back(d.R[3 * r + 2]);
+                    P->grp_rho.push_back(xi);
                     ++acc;
                 }
         }
+        P->max_nR = std::max(P->max_nR, d.n_R);
+        P->max_nn = std::max(P->max_nn, (long long)d.n_orb * d.n_orb);
         P->grp_start.push_back(acc);
         md.neg_first = (int)P->negr.size();
         std::map<std::tuple<int, int, int>, int> idx;
@@ -237,16 +246,25 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
     std::vector<std::vector<BlockItem>> cls_blocks(kNumClasses);
     auto flush = [&]() {
         if (cur.pencil_count == 0) return;
+        cur.grange_begin = (int)P->granges.size();
         for (int c = 0; c < kNumClasses; ++c) {
             cur.cls[c].begin = (int)P->blocks.size();
             cur.cls[c].count = (int)cls_blocks[c].size();
             cur.cls_kpts[c] = 0;
             for (auto& b : cls_blocks[c]) {
+                const int bi = (int)P->blocks.size();
+                if (P->granges.size() > (size_t)cur.grange_begin &&
+                    P->granges.back().model == b.model &&
+                    P->granges.back().begin + P->granges.back().count == bi)
+                    P->granges.back().count++;
+                else
+                    P->granges.push_back(GaccRange{b.model, bi, 1, 0});
                 P->blocks.push_back(b);
                 cur.cls_kpts[c] += b.count;
             }
             cls_blocks[c].clear();
         }
+        cur.grange_count = (int)P->granges.size() - cur.grange_begin;
         max_t = std::max(max_t, cur.tbytes);
         max_p = std::max(max_p, cur.pbytes);
         P->chunks.push_back(cur);
@@ -284,6 +302,8 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
     append_blob(P->blob, P->tab_off[6], P->negr);
     append_blob(P->blob, P->tab_off[7], P->pencils);
     append_blob(P->blob, P->tab_off[8], P->blocks);
+    append_blob(P->blob, P->tab_off[9], P->grp_rho);
+    append_blob(P->blob, P->tab_off[10], P->granges);
 
     size_t off = kAlign;  // status word
     P->off_tables = off;
@@ -428,7 +448,82 @@ kubo_status enqueue_forward(kubo_plan_s* P, const double* t, const double* ef, d
     return KUBO_OK;
 }
 
+kubo_status enqueue_backward(kubo_plan_s* P, const double* t, const double* ef, double eta,
+                             double kT, const double* sbar, double* grad, unsigned char* ws,
+                             hipStream_t s) {
+    const Tables tb = device_tables(P, ws);
+    unsigned* status = reinterpret_cast<unsigned*>(ws);
+    double* tp = reinterpret_cast<double*>(ws + P->off_tp);
+    double* tbuf = reinterpret_cast<double*>(ws + P->off_tbuf);
+    double* pbuf = reinterpret_cast<double*>(ws + P->off_pbuf);
+    HIP_TRY(launch_clear(status, s));
+    HIP_TRY(launch_hermproj(tb, P->n_models, P->t_elems, t, tp, s));
+    HIP_TRY(launch_zero(grad, 2 * P->t_elems, s));
+    for (const Chunk& c : P->chunks) {
+        HIP_TRY(launch_pencil(tb, c.pencil_begin, c.pencil_count, tp, tbuf, s));
+        for (int k = 0; k < kNumClasses; ++k) {
+            if (c.cls[k].count == 0) continue;
+            AdjLaunch L;
+            L.tb = tb;
+            L.tbuf = tbuf;
+            L.pbuf = pbuf;
+            L.e_fermi = ef;
+            L.sbar = sbar;
+            L.status = status;
+            L.eta = eta;
+            L.kT = kT;
+            L.nF = P->nF;
+            L.max_sweeps = (P->flags & KUBO_F_DEBUG_SWEEPCAP) ? 1 : kMaxSweeps;
+            L.item_begin = c.cls[k].begin;
+            L.item_count = c.cls[k].count;
+            L.np = kClasses[k].np;
+            L.max_groups = P->max_groups;
+            TimedScope ts(P, s, 1, c.cls_kpts[k]);
+            HIP_TRY(launch_adjoint(L, s));
+            ts.finish();
+        }
+        HIP_TRY(launch_gacc(tb, tb.granges, c.grange_begin, c.grange_count, P->max_nR, P->max_nn,
+                            pbuf, grad, s));
+    }
+    HIP_TRY(launch_gsym(tb, P->n_models, P->t_elems, grad, s));
+    return KUBO_OK;
+}
+
 bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
+
+// Capture the launch sequence into a hipGraph on first use (or when the key
+// changes), then replay it.
+template <class F>
+kubo_status run_graph(kubo_plan_s* plan, CachedGraph& g, const GraphKey& key, hipStream_t s,
+                      F&& enqueue) {
+    if (!(g.valid && g.key == key)) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+        g = CachedGraph();
+        HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        plan->capturing = true;
+        kubo_status st = enqueue();
+        plan->capturing = false;
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(s, &graph);
+        if (st != KUBO_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess) return KUBO_E_HIP;
+        hipGraphExec_t exec = nullptr;
+        if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return KUBO_E_HIP;
+        }
+        g.graph = graph;
+        g.exec = exec;
+        g.key = key;
+        g.valid = true;
+    }
+    HIP_TRY(hipGraphLaunch(g.exec, s));
+    return KUBO_OK;
+}
 
 }  // namespace
 
@@ -471,34 +566,9 @@ kubo_status kubo_ahc(kubo_plan_t plan, const double* t, const double* e_fermi, d
         key.d[0] = eta;
         key.d[1] = kT;
         key.stream = stream;
-        CachedGraph& g = plan->graph_fwd;
-        if (!(g.valid && g.key == key)) {
-            if (g.exec) (void)hipGraphExecDestroy(g.exec);
-            if (g.graph) (void)hipGraphDestroy(g.graph);
-            g = CachedGraph();
-            HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            plan->capturing = true;
-            st = enqueue_forward(plan, t, e_fermi, eta, kT, sigma, ws, s);
-            plan->capturing = false;
-            hipGraph_t graph = nullptr;
-            hipError_t e = hipStreamEndCapture(s, &graph);
-            if (st != KUBO_OK) {
-                if (graph) (void)hipGraphDestroy(graph);
-                return st;
-            }
-            if (e != hipSuccess) return KUBO_E_HIP;
-            hipGraphExec_t exec = nullptr;
-            if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
-                (void)hipGraphDestroy(graph);
-                return KUBO_E_HIP;
-            }
-            g.graph = graph;
-            g.exec = exec;
-            g.key = key;
-            g.valid = true;
-        }
-        HIP_TRY(hipGraphLaunch(g.exec, s));
-        return KUBO_OK;
+        return run_graph(plan, plan->graph_fwd, key, s, [&]() {
+            return enqueue_forward(plan, t, e_fermi, eta, kT, sigma, ws, s);
+        });
     }
     return enqueue_forward(plan, t, e_fermi, eta, kT, sigma, ws, s);
 }
@@ -509,8 +579,25 @@ kubo_status kubo_ahc_backward(kubo_plan_t plan, const double* t, const double* e
     if (!plan || !t || !e_fermi || !sigma_bar || !grad_t) return KUBO_E_INVALID;
     if (!finite_nonneg(eta) || !finite_nonneg(kT) || !(eta > 0.0)) return KUBO_E_INVALID;
     if (!workspace || workspace_bytes < plan->total) return KUBO_E_WORKSPACE;
-    (void)stream;
-    return KUBO_E_UNSUPPORTED;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    unsigned char* ws = static_cast<unsigned char*>(workspace);
+    kubo_status st = ensure_tables(plan, workspace, s);
+    if (st != KUBO_OK) return st;
+    if ((plan->flags & KUBO_F_GRAPH) && s != nullptr) {
+        GraphKey key{};
+        key.p[0] = t;
+        key.p[1] = e_fermi;
+        key.p[2] = sigma_bar;
+        key.p[3] = workspace;
+        key.p[4] = grad_t;
+        key.d[0] = eta;
+        key.d[1] = kT;
+        key.stream = stream;
+        return run_graph(plan, plan->graph_bwd, key, s, [&]() {
+            return enqueue_backward(plan, t, e_fermi, eta, kT, sigma_bar, grad_t, ws, s);
+        });
+    }
+    return enqueue_backward(plan, t, e_fermi, eta, kT, sigma_bar, grad_t, ws, s);
 }
 
 kubo_status kubo_plan_device_status(kubo_plan_t plan, const void* workspace, void* stream) {
@@ -564,8 +651,10 @@ void kubo_plan_destroy(kubo_plan_t plan) {
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);
     }
-    if (plan->graph_fwd.exec) (void)hipGraphExecDestroy(plan->graph_fwd.exec);
-    if (plan->graph_fwd.graph) (void)hipGraphDestroy(plan->graph_fwd.graph);
+    for (CachedGraph* g : {&plan->graph_fwd, &plan->graph_bwd}) {
+        if (g->exec) (void)hipGraphExecDestroy(g->exec);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+    }
     delete plan;
 }
 

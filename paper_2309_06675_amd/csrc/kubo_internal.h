@@ -45,6 +45,11 @@ struct BlockItem {
     long long pbuf_off;  // adjoint: its pencil-sum matrices (chunk-relative)
 };
 
+// A run of consecutive k-blocks of one model (the adjoint's transposed Bloch sum).
+struct GaccRange {
+    int model, begin, count, pad;
+};
+
 // Device pointers of the tables uploaded into the workspace.
 struct Tables {
     const ModelDev* models;
@@ -53,9 +58,11 @@ struct Tables {
     const int* grp_r;
     const int* grp_R1;
     const int* grp_R2;
+    const int* grp_rho;   // index of the R_x group of each grouped entry
     const int* negr;
     const PencilItem* pencils;
     const BlockItem* blocks;
+    const GaccRange* granges;
 };
 
 }  // namespace kubo

@@ -21,6 +21,21 @@ struct FwdLaunch {
     int max_groups;  // persistent grid size cap
 };
 
+struct AdjLaunch {
+    Tables tb;
+    const double* tbuf;
+    double* pbuf;
+    const double* e_fermi;
+    const double* sbar;
+    unsigned* status;
+    double eta, kT;
+    int nF;
+    int max_sweeps;
+    int item_begin, item_count;
+    int np;
+    int max_groups;
+};
+
 hipError_t launch_clear(unsigned* status, hipStream_t s);
 hipError_t launch_zero(double* p, long long count, hipStream_t s);
 hipError_t launch_hermproj(const Tables& tb, int n_models, long long total, const double* t,
@@ -28,6 +43,12 @@ hipError_t launch_hermproj(const Tables& tb, int n_models, long long total, cons
 hipError_t launch_pencil(const Tables& tb, int item_begin, int item_count, const double* tp,
                          double* tbuf, hipStream_t s);
 hipError_t launch_forward(const FwdLaunch& L, hipStream_t s);
+hipError_t launch_adjoint(const AdjLaunch& L, hipStream_t s);
+hipError_t launch_gacc(const Tables& tb, const GaccRange* ranges, int range_begin, int range_count,
+                       int max_nR, long long max_nn, const double* pbuf, double* grad,
+                       hipStream_t s);
+hipError_t launch_gsym(const Tables& tb, int n_models, long long total, double* grad,
+                       hipStream_t s);
 hipError_t launch_reduce(const Tables& tb, int n_models, int nF, const double* partial,
                          double* sigma, unsigned* status, hipStream_t s);
 

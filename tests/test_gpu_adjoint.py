@@ -1,0 +1,184 @@
+"""GPU adjoint (kubo_ahc_backward through the C ABI): against the oracle's reference
+gradient and against central finite differences of the GPU forward."""
+
+import numpy as np
+import pytest
+
+from paper_2309_06675_amd import kubo, synth
+
+from _util import workload_fermi
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+
+    assert _t.cuda.is_available(), "GPU tests need a visible MI355X"
+    return _t
+
+
+def gpu_grad(torch, models, grid, ef, eta, kT, sbar, slabs=None, flags=0):
+    plan = kubo.Plan(models, grid=grid, n_fermi=ef.shape[-1], slabs=slabs, flags=flags)
+    t = kubo.to_device_t(models)
+    efd = torch.from_numpy(np.ascontiguousarray(np.tile(ef, (len(models), 1)))).to("cuda")
+    sb = torch.from_numpy(np.ascontiguousarray(np.tile(sbar, (len(models), 1)))).to("cuda")
+    g = plan.backward(t, efd, eta, kT, sb)
+    st = plan.device_status()
+    assert st == kubo.KUBO_OK, kubo.kubo_status_string(st)
+    return g.cpu().numpy(), plan, t, efd, sb
+
+
+def assert_grad_close(got, ref, rel, what=""):
+    scale = np.abs(ref).max()
+    err = np.abs(got - ref)
+    bound = rel * np.maximum(np.abs(ref), 1e-3 * scale)
+    bad = np.nonzero(err > bound)[0]
+    assert bad.size == 0, (f"{what}: {bad.size} of {err.size} entries off; worst rel "
+                           f"{(err / np.maximum(np.abs(ref), 1e-3 * scale)).max():.3e}")
+
+
+@pytest.mark.parametrize("n,L,grid,kT,eta", [(3, 1, (3, 3, 2), 0.05, 0.05),
+                                             (8, 1, (4, 3, 2), 0.02, 0.01),
+                                             (13, 1, (3, 2, 2), 0.03, 0.02),
+                                             (32, 1, (2, 3, 2), 0.01, 0.01)])
+def test_gradient_matches_oracle(torch, oracle, n, L, grid, kT, eta):
+    m = synth.random_model(n, L, 1.0, 700 + n)
+    lo, hi = oracle.band_range(m.t, m.R, (3, 3, 3))
+    ef = np.linspace(lo, hi, 5)
+    sbar = np.array([0.3, -1.0, 0.8, 0.5, -0.2])
+    print(f"case grad n={n}", flush=True)
+    got, *_ = gpu_grad(torch, [m], grid, ef, eta, kT, sbar)
+    ref = oracle.ahc_grad(m.t, m.R, grid, ef, eta, kT, sbar).reshape(-1)
+    assert_grad_close(got, ref, 1e-9, f"n={n}")
+
+
+def test_gradient_through_exact_degeneracy(torch, oracle):
+    m = synth.doubled(synth.random_model(5, 1, 1.0, 808))
+    ef = np.array([-0.5, 0.4, 1.1])
+    sbar = np.array([1.0, -0.7, 0.2])
+    got, *_ = gpu_grad(torch, [m], (3, 3, 2), ef, 0.05, 0.05, sbar)
+    ref = oracle.ahc_grad(m.t, m.R, (3, 3, 2), ef, 0.05, 0.05, sbar).reshape(-1)
+    assert np.all(np.isfinite(got))
+    assert_grad_close(got, ref, 1e-8, "doubled")
+
+
+def test_gradient_slab_and_symmetry(torch, oracle):
+    m = synth.random_model(6, 2, 1.0, 818)
+    grid = (5, 4, 3)
+    ef = np.array([-1.0, 0.0, 2.0])
+    sbar = np.array([0.4, 1.0, -0.6])
+    got, *_ = gpu_grad(torch, [m], grid, ef, 0.02, 0.03, sbar, slabs=[(7, 29)])
+    ref = oracle.ahc_grad(m.t, m.R, grid, ef, 0.02, 0.03, sbar, k_begin=7, k_count=29)
+    assert_grad_close(got, ref.reshape(-1), 1e-9, "slab")
+    G = got.reshape(m.t.shape)
+    idx = {tuple(v): i for i, v in enumerate(m.R)}
+    for i, v in enumerate(m.R):
+        assert np.array_equal(G[idx[tuple(-v)]], G[i].conj().T)
+
+
+def test_cfg3_model_oracle_gradient_on_8cubed(torch, oracle):
+    wl = synth.workload(3)
+    m = wl.models[0]
+    ef = workload_fermi(3, wl)[0]
+    sbar = synth.normals(3333, wl.n_fermi)
+    grid = (8, 8, 8)
+    print("case cfg3 model, 8^3 grid", flush=True)
+    got, *_ = gpu_grad(torch, [m], grid, ef, wl.eta_adjoint, wl.kT, sbar)
+    ref = oracle.ahc_grad(m.t, m.R, grid, ef, wl.eta_adjoint, wl.kT, sbar).reshape(-1)
+    assert_grad_close(got, ref, 1e-8, "cfg3 8^3")
+
+
+def _fd_setup(torch):
+    wl = synth.workload(3)
+    m = wl.models[0]
+    ef = workload_fermi(3, wl)[0]
+    sbar = synth.normals(3334, wl.n_fermi)
+    got, plan, t, efd, sb = gpu_grad(torch, [m], wl.grid, ef, wl.eta_adjoint, wl.kT, sbar)
+    G = got.reshape(m.t.shape)
+    sbar_t = torch.from_numpy(sbar).to("cuda")
+    tp = t.clone()
+    tv = tp.view(m.t.shape)
+
+    def loss_at(r, i, j, step):
+        orig = tv[r, i, j].clone()
+        tv[r, i, j] = orig + step
+        s = plan.forward(tp, efd, wl.eta_adjoint, wl.kT)[0]
+        val = float((sbar_t * s).sum().item())
+        tv[r, i, j] = orig
+        return val
+
+    entries = []
+    for a, b, c, d in synth.uniform01(3335, 200).reshape(50, 4):
+        entries.append((int(a * m.n_R), int(b * m.n), int(c * m.n), int(d * 2)))
+    return m, G, loss_at, entries
+
+
+def test_cfg3_finite_differences_50_entries(torch):
+    """Central differences with the config's step h = 1e-6 on 50 random hoppings of the
+    config-3 model over its full 64^3 grid.  At this step the FD error is dominated by the
+    forward's own FP64 noise divided by 2h, so small entries are judged against a floor of
+    0.1 max|G| (see the design notes); the Richardson test below is tight entry-wise."""
+    m, G, loss_at, entries = _fd_setup(torch)
+    h = 1e-6
+    an, fd = [], []
+    for (r, i, j, part) in entries:
+        step = h if part == 0 else 1j * h
+        fd.append((loss_at(r, i, j, step) - loss_at(r, i, j, -step)) / (2 * h))
+        an.append(G[r, i, j].real if part == 0 else G[r, i, j].imag)
+    an, fd = np.array(an), np.array(fd)
+    scale = np.abs(G).max()
+    rel = np.abs(an - fd) / np.maximum(np.abs(fd), 0.1 * scale)
+    print("fd(1e-6) rel errors: max %.3e median %.3e" % (rel.max(), np.median(rel)), flush=True)
+    assert rel.max() <= 1e-6, rel.max()
+
+
+def test_cfg3_richardson_differences_entrywise(torch):
+    """Richardson-extrapolated central differences (h = 1e-4 and 2e-4; error O(h^4)) on 20
+    of the same hoppings, entry-wise at 1e-6 against max(|G_FD|, 1e-3 max|G|)."""
+    m, G, loss_at, entries = _fd_setup(torch)
+    h = 1e-4
+    an, fd = [], []
+    for (r, i, j, part) in entries[:20]:
+        unit = 1.0 if part == 0 else 1j
+        d1 = (loss_at(r, i, j, h * unit) - loss_at(r, i, j, -h * unit)) / (2 * h)
+        d2 = (loss_at(r, i, j, 2 * h * unit) - loss_at(r, i, j, -2 * h * unit)) / (4 * h)
+        fd.append((4 * d1 - d2) / 3)
+        an.append(G[r, i, j].real if part == 0 else G[r, i, j].imag)
+    an, fd = np.array(an), np.array(fd)
+    scale = np.abs(G).max()
+    rel = np.abs(an - fd) / np.maximum(np.abs(fd), 1e-3 * scale)
+    print("richardson rel errors: max %.3e median %.3e" % (rel.max(), np.median(rel)), flush=True)
+    assert rel.max() <= 1e-6, rel.max()
+
+
+def test_autograd_function(torch):
+    m = synth.random_model(8, 1, 1.0, 909)
+    grid = (4, 3, 3)
+    plan = kubo.Plan([m], grid=grid, n_fermi=3)
+    t = kubo.to_device_t([m]).requires_grad_(True)
+    ef = torch.tensor([[-1.0, 0.0, 1.0]], dtype=torch.float64, device="cuda")
+    sig = kubo.ahc(t, plan, ef, 0.02, 0.02)
+    w = torch.tensor([[1.0, -2.0, 0.5]], dtype=torch.float64, device="cuda")
+    (sig * w).sum().backward()
+    direct = plan.backward(t.detach(), ef, 0.02, 0.02, w)
+    assert torch.equal(t.grad, direct)
+
+
+def test_backward_graph_replay(torch):
+    m = synth.random_model(10, 1, 1.0, 919)
+    grid = (4, 4, 2)
+    ef = torch.tensor([[-1.0, 0.5]], dtype=torch.float64, device="cuda")
+    sb = torch.tensor([[0.7, 1.0]], dtype=torch.float64, device="cuda")
+    t = kubo.to_device_t([m])
+    ref = kubo.Plan([m], grid=grid, n_fermi=2).backward(t, ef, 0.02, 0.02, sb)
+    g = kubo.Plan([m], grid=grid, n_fermi=2, flags=kubo.KUBO_F_GRAPH)
+    s = torch.cuda.Stream()
+    out = torch.empty_like(t)
+    with torch.cuda.stream(s):
+        for rep in range(3):
+            out.fill_(complex(float("nan"), 0.0))
+            g.backward(t, ef, 0.02, 0.02, sb, out=out)
+            torch.cuda.synchronize()
+            assert torch.equal(out, ref), rep
