@@ -84,8 +84,9 @@ typedef struct {
                                     while the pointers and scalars stay the same */
 #define KUBO_F_TIMING 0x2u       /* record HIP events around every launch of the per-k
                                     kernels (ignored while KUBO_F_GRAPH replays) */
-#define KUBO_F_DEBUG_SWEEPCAP 0x100u /* cap the eigensolver at one sweep, so that the device
-                                    status reports KUBO_E_NOCONV (tests of that path) */
+#define KUBO_F_DEBUG_SWEEPCAP 0x100u /* cap the iterative eigensolver at one iteration (one
+                                    sweep) and route every k-point through it, so that the
+                                    device status reports KUBO_E_NOCONV (tests of that path) */
 
 /*
  * kubo_plan -- validate the models and build the host-side plan.  No device

@@ -1,0 +1,76 @@
+// kubo_cplx.h -- device helpers shared by the HIP kernels: complex FP64
+// arithmetic on double2 (x = re, y = im), exact-angle unit phases and the
+// occupation function.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace kubo {
+
+// ---------------------------------------------------------------------------
+// complex helpers (double2: x = re, y = im)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double2 c_make(double r, double i) { return make_double2(r, i); }
+__device__ __forceinline__ double2 c_add(double2 a, double2 b) { return c_make(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 c_sub(double2 a, double2 b) { return c_make(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 c_conj(double2 a) { return c_make(a.x, -a.y); }
+__device__ __forceinline__ double2 c_scale(double s, double2 a) { return c_make(s * a.x, s * a.y); }
+__device__ __forceinline__ double2 c_mul(double2 a, double2 b) {
+    return c_make(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// acc + a * b
+__device__ __forceinline__ double2 c_fma(double2 a, double2 b, double2 acc) {
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(-a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(a.y, b.x, acc.y);
+    return acc;
+}
+// acc + conj(a) * b
+__device__ __forceinline__ double2 c_fmac(double2 a, double2 b, double2 acc) {
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(-a.y, b.x, acc.y);
+    return acc;
+}
+// i * a
+__device__ __forceinline__ double2 c_i(double2 a) { return c_make(-a.y, a.x); }
+
+// e^{2 pi i m / N} for an integer residue m (reduced to (-N/2, N/2] first).
+__device__ __forceinline__ double2 unit_phase(long long m, long long N) {
+    m %= N;
+    if (m < 0) m += N;
+    if (2 * m > N) m -= N;
+    double s, c;
+    sincospi(2.0 * (double)m / (double)N, &s, &c);
+    return c_make(c, s);
+}
+
+// e^{i (2 pi a1/N1 + 2 pi a2/N2)} with exact rational reduction of the angle.
+__device__ __forceinline__ double2 unit_phase2(long long a1, long long N1, long long a2,
+                                               long long N2) {
+    long long m1 = a1 % N1, m2 = a2 % N2;
+    return unit_phase(m1 * N2 + m2 * N1, N1 * N2);
+}
+
+// Occupation: Fermi-Dirac at kT > 0, a step with f(E_F) = 1/2 at kT = 0.
+__device__ __forceinline__ double occupation(double e, double ef, double kT) {
+    if (kT == 0.0) return e < ef ? 1.0 : (e > ef ? 0.0 : 0.5);
+    double u = (e - ef) / kT;
+    if (u > 0.0) {
+        double w = exp(-u);
+        return w / (1.0 + w);
+    }
+    return 1.0 / (1.0 + exp(u));
+}
+
+// conj(a) * b  and  a * conj(b)
+__device__ __forceinline__ double2 c_cmul(double2 a, double2 b) {
+    return c_make(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ double2 c_mulc(double2 a, double2 b) {
+    return c_make(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+
+}  // namespace kubo

@@ -440,7 +440,7 @@ kubo_status enqueue_forward(kubo_plan_s* P, const double* t, const double* ef, d
             L.np = kClasses[k].np;
             L.max_groups = P->max_groups;
             TimedScope ts(P, s, 0, c.cls_kpts[k]);
-            HIP_TRY(launch_forward(L, s));
+            HIP_TRY(launch_forward_wave(L, s));
             ts.finish();
         }
     }

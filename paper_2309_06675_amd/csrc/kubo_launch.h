@@ -43,6 +43,7 @@ hipError_t launch_hermproj(const Tables& tb, int n_models, long long total, cons
 hipError_t launch_pencil(const Tables& tb, int item_begin, int item_count, const double* tp,
                          double* tbuf, hipStream_t s);
 hipError_t launch_forward(const FwdLaunch& L, hipStream_t s);
+hipError_t launch_forward_wave(const FwdLaunch& L, hipStream_t s);
 hipError_t launch_adjoint(const AdjLaunch& L, hipStream_t s);
 hipError_t launch_gacc(const Tables& tb, const GaccRange* ranges, int range_begin, int range_count,
                        int max_nR, long long max_nn, const double* pbuf, double* grad,

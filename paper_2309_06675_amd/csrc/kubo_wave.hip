@@ -1,0 +1,577 @@
+// kubo_wave.hip -- one wavefront per k-point: the forward pipeline for n <= 32.
+//
+// Eigensolver: the route the paper batched from EISPACK for complex Hermitian
+// matrices (Householder reduction to a real symmetric tridiagonal matrix,
+// implicit QL iterations with eigenvector accumulation, back-transformation),
+// restated for a 64-lane wavefront instead of one vector lane per matrix:
+//   * Householder: lane r owns row r of the trailing block; the reflector of
+//     column k is chosen so the sub-diagonal element is real, making T real.
+//   * QL: the tridiagonal (d, e) lives one element per lane; the rotation
+//     chain reads and writes lanes by index (uniform across the wave), and the
+//     rotations of a sweep are applied to Z afterwards, one row per lane, in a
+//     single streaming pass.
+//   * Back-transformation U = H_0 ... H_{n-2} Z: lane c owns column c.
+// Velocities: W = v U with v built on the fly from the pencil partial sums,
+// then U^+ W accumulated in registers, so A = U^+ v_x U and B = U^+ v_y U
+// never need their own LDS buffers; the curvature is taken straight from the
+// register tiles.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "kubo_cplx.h"
+#include "kubo_internal.h"
+#include "kubo_launch.h"
+
+namespace kubo {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// value of a per-lane register held by lane `src` (src must be wave-uniform)
+__device__ __forceinline__ double lane_read(double v, int src) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), src);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), src);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+template <int NP>
+struct WaveLds {
+    static constexpr int LD = NP + 1;
+    double2 P[NP * LD];  // H, then the Householder vectors, then W = v U
+    double2 U[NP * LD];  // Z (real parts) during QL, then U
+    double2 tau[NP];
+    double2 wv[NP];
+    double cs[2 * NP];
+    double2 de2[NP];  // (d_i, e_i) of the tridiagonal matrix, zero past n
+    double E[NP];
+    double Om[NP];
+    double2 ph[16];
+};
+
+// Reduce the Hermitian matrix in S.P (n x n) to real tridiagonal form.
+// On return lane i holds d_i and e_i (e_{n-1} = 0); the Householder vector of
+// step k is stored in column k below the diagonal (row k+1 holds 1) and its
+// scalar in S.tau[k]; H = Q T Q^+ with Q = H_0 H_1 ... H_{n-2},
+// H_k = I - tau_k v_k v_k^+.
+template <int NP>
+__device__ void wave_tridiag(WaveLds<NP>& S, int n, double& d_lane, double& e_lane) {
+    constexpr int LD = WaveLds<NP>::LD;
+    const int r = threadIdx.x & 63;
+    d_lane = 0.0;
+    e_lane = 0.0;
+    for (int k = 0; k < n - 1; ++k) {
+        const bool act = (r > k) && (r < n);
+        const double2 x = act ? S.P[r * LD + k] : c_make(0.0, 0.0);
+        const double2 alpha = S.P[(k + 1) * LD + k];
+        const double dk = S.P[k * LD + k].x;
+        double xn2 = (act && r > k + 1) ? (x.x * x.x + x.y * x.y) : 0.0;
+        xn2 = wave_sum(xn2);
+        double beta;
+        double2 tau, scal;
+        if (xn2 == 0.0 && alpha.y == 0.0) {
+            beta = alpha.x;
+            tau = c_make(0.0, 0.0);
+            scal = c_make(0.0, 0.0);
+        } else {
+            const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn2);
+            beta = -copysign(nrm, alpha.x);
+            tau = c_make((beta - alpha.x) / beta, -alpha.y / beta);
+            // 1 / (alpha - beta)
+            const double ar = alpha.x - beta, ai = alpha.y;
+            const double den = 1.0 / (ar * ar + ai * ai);
+            scal = c_make(ar * den, -ai * den);
+        }
+        const double2 v = (r == k + 1) ? c_make(1.0, 0.0) : (act ? c_mul(x, scal) : c_make(0.0, 0.0));
+        if (r == k) {
+            d_lane = dk;
+            e_lane = beta;
+        }
+        __syncthreads();
+        if (act) S.P[r * LD + k] = v;
+        if (r == 0) S.tau[k] = tau;
+        __syncthreads();
+        if (tau.x == 0.0 && tau.y == 0.0) continue;
+        // p = A22 v (row r)
+        double2 p = c_make(0.0, 0.0);
+        if (act)
+            for (int c = k + 1; c < n; ++c) p = c_fma(S.P[r * LD + c], S.P[c * LD + k], p);
+        const double mu = wave_sum(act ? (v.x * p.x + v.y * p.y) : 0.0);  // v^+ p (real)
+        const double t2 = 0.5 * (tau.x * tau.x + tau.y * tau.y) * mu;
+        const double2 w = c_sub(c_mul(tau, p), c_scale(t2, v));
+        if (act) S.wv[r] = w;
+        __syncthreads();
+        if (act) {
+            for (int c = k + 1; c < n; ++c) {
+                const double2 vc = S.P[c * LD + k], wc = S.wv[c];
+                double2 a = S.P[r * LD + c];
+                a = c_sub(a, c_add(c_mulc(v, wc), c_mulc(w, vc)));
+                S.P[r * LD + c] = a;
+            }
+        }
+        __syncthreads();
+    }
+    if (r == n - 1) {
+        d_lane = S.P[(n - 1) * LD + (n - 1)].x;
+        e_lane = 0.0;
+    }
+    __syncthreads();
+}
+
+// Implicit QL with shifts on (d, e), one element per lane; accumulates the
+// rotations into Z (real parts of S.U, identity on entry, lane = row).
+// Returns false if some eigenvalue needed more than max_iter iterations.
+template <int NP>
+__device__ bool wave_ql(WaveLds<NP>& S, int n, double& d_lane, double& e_lane, int max_iter) {
+    constexpr int LD = WaveLds<NP>::LD;
+    const int lane = threadIdx.x & 63;
+    bool ok = true;
+    double f = 0.0, tst1 = 0.0;
+    for (int l = 0; l < n; ++l) {
+        int iter = 0;
+        {
+            const double dl = lane_read(d_lane, l), el = lane_read(e_lane, l);
+            tst1 = fmax(tst1, fabs(dl) + fabs(el));
+        }
+        for (;;) {
+            const bool small = (lane >= l) && (lane < n) && (tst1 + fabs(e_lane) == tst1);
+            const unsigned long long mask = __ballot(small);
+            if (mask == 0ull) {  // only possible with NaN input: e_{n-1} = 0 always qualifies
+                ok = false;
+                break;
+            }
+            const int m = __ffsll((long long)mask) - 1;
+            if (m <= l) break;
+            if (++iter > max_iter) {
+                ok = false;
+                break;
+            }
+            // shift from the leading 2x2 block
+            const double g0 = lane_read(d_lane, l);
+            const double el = lane_read(e_lane, l);
+            const double dnext = lane_read(d_lane, l + 1);
+            double p = (dnext - g0) / (2.0 * el);
+            double r = sqrt(p * p + 1.0);
+            const double pr = p + copysign(r, p);
+            const double new_dl = el / pr;
+            const double dl1 = el * pr;
+            double h = g0 - new_dl;
+            if (lane >= l + 2 && lane < n) d_lane -= h;
+            if (lane == l) d_lane = new_dl;
+            if (lane == l + 1) d_lane = dl1;
+            f += h;
+            // QL sweep, i = m-1 down to l
+            p = lane_read(d_lane, m);
+            double c = 1.0, c2 = 1.0, c3 = 1.0, s = 0.0, s2 = 0.0;
+            const double el1 = lane_read(e_lane, l + 1);
+            for (int i = m - 1; i >= l; --i) {
+                c3 = c2;
+                c2 = c;
+                s2 = s;
+                const double ei = lane_read(e_lane, i);
+                const double di = lane_read(d_lane, i);
+                const double g = c * ei;
+                h = c * p;
+                r = sqrt(p * p + ei * ei);
+                const double e_ip1 = s * r;
+                const double inv = 1.0 / r;
+                s = ei * inv;
+                c = p * inv;
+                p = c * di - s * g;
+                const double d_ip1 = h + s * (c * g + s * di);
+                if (lane == i + 1) {
+                    e_lane = e_ip1;
+                    d_lane = d_ip1;
+                }
+                if (lane == 0) {
+                    S.cs[2 * i] = c;
+                    S.cs[2 * i + 1] = s;
+                }
+            }
+            p = -s * s2 * c3 * el1 * el / dl1;
+            if (lane == l) {
+                e_lane = s * p;
+                d_lane = c * p;
+            }
+            __syncthreads();
+            // apply the sweep to Z: rotation i mixes columns i and i+1
+            if (lane < n) {
+                double carry = S.U[lane * LD + m].x;
+                for (int i = m - 1; i >= l; --i) {
+                    const double ci = S.cs[2 * i], si = S.cs[2 * i + 1];
+                    const double zi = S.U[lane * LD + i].x;
+                    S.U[lane * LD + i + 1].x = si * zi + ci * carry;
+                    carry = ci * zi - si * carry;
+                }
+                S.U[lane * LD + l].x = carry;
+            }
+            __syncthreads();
+        }
+        if (lane == l) d_lane += f;
+        if (!ok) break;
+    }
+    return ok;
+}
+
+// Eigenvalues of the real symmetric tridiagonal (d, e) in S.de2 by bisection.
+// Lanes 2j and 2j+1 search eigenvalue j (ascending): each step they count at
+// the two interior trisection points of [lo, hi] and keep the third that holds
+// eigenvalue j.  A fixed number of steps shrinks the Gershgorin interval below
+// 4 eps max|lambda|.  Returns lambda_j in both lanes.
+template <int NP>
+__device__ double wave_bisect(const WaveLds<NP>& S, int n, double glo, double ghi, double pivmin) {
+    const int lane = threadIdx.x & 63;
+    const int j = lane >> 1;
+    const int half = lane & 1;
+    double lo = glo, hi = ghi;
+    const double scale = fmax(fabs(glo), fabs(ghi));
+    const double tol = 4.0 * 2.220446049250313e-16 * scale + 1e-300;
+    int steps = 0;
+    for (double w = ghi - glo; w > tol && steps < 80; w *= (1.0 / 3.0)) ++steps;
+    for (int it = 0; it < steps; ++it) {
+        const double third = (hi - lo) * (1.0 / 3.0);
+        const double x = half ? (hi - third) : (lo + third);
+        // Sturm count at x
+        int cnt = 0;
+        double q = 1.0, e2prev = 0.0;
+        for (int i = 0; i < n; ++i) {
+            const double2 de = S.de2[i];
+            // reciprocal estimate refined by one Newton step (full FP64 precision)
+            double rq = __builtin_amdgcn_rcp(q);
+            rq = fma(rq, fma(-q, rq, 1.0), rq);
+            double qi = (de.x - x) - e2prev * rq;
+            if (fabs(qi) < pivmin) qi = -pivmin;
+            cnt += (qi < 0.0) ? 1 : 0;
+            q = qi;
+            e2prev = de.y * de.y;
+        }
+        const int cother = __shfl_xor(cnt, 1, 64);
+        const int c1 = half ? cother : cnt;  // count at lo + third
+        const int c2 = half ? cnt : cother;  // count at hi - third
+        const double x1 = lo + third, x2 = hi - third;
+        if (c1 > j) {
+            hi = x1;
+        } else if (c2 > j) {
+            lo = x1;
+            hi = x2;
+        } else {
+            lo = x2;
+        }
+    }
+    return 0.5 * (lo + hi);
+}
+
+// Eigenvector of the tridiagonal matrix for an isolated eigenvalue lam by the
+// twisted factorisation of T - lam I: forward pivots dp, backward pivots dm,
+// twist index r = argmin |dp_r + dm_r - (d_r - lam)|, then z_r = 1 and the two
+// one-sided recurrences.  Returns the normalised vector in z[0..NP).
+template <int NP>
+__device__ void wave_twisted(const WaveLds<NP>& S, int n, double lam, double pivmin,
+                             double (&z)[NP]) {
+    double dp[NP], dm[NP];
+    {
+        double q = 1.0, e2prev = 0.0;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const double2 de = S.de2[i];
+            double qi = (de.x - lam) - e2prev / q;
+            if (fabs(qi) < pivmin) qi = -pivmin;
+            dp[i] = qi;
+            q = qi;
+            e2prev = de.y * de.y;
+        }
+    }
+    {
+        double q = 1.0;
+#pragma unroll
+        for (int i = NP - 1; i >= 0; --i) {
+            const double2 de = S.de2[i];
+            double qi = (de.x - lam) - ((i < n - 1) ? de.y * de.y / q : 0.0);
+            if (fabs(qi) < pivmin) qi = -pivmin;
+            dm[i] = qi;
+            q = qi;
+        }
+    }
+    int r = 0;
+    double best = 1e308;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        if (i < n) {
+            const double g = fabs(dp[i] + dm[i] - (S.de2[i].x - lam));
+            if (g < best) {
+                best = g;
+                r = i;
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NP; ++i) z[i] = (i == r) ? 1.0 : 0.0;
+    // below the twist: z_i = -(e_i / dp_i) z_{i+1}
+#pragma unroll
+    for (int i = NP - 2; i >= 0; --i) {
+        const double ei = S.de2[i].y;
+        const double v = -(ei / dp[i]) * z[i + 1];
+        if (i < r) z[i] = v;
+    }
+    // above the twist: z_i = -(e_{i-1} / dm_i) z_{i-1}
+#pragma unroll
+    for (int i = 1; i < NP; ++i) {
+        const double ei = S.de2[i - 1].y;
+        const double v = -(ei / dm[i]) * z[i - 1];
+        if (i > r && i < n) z[i] = v;
+    }
+    double nrm = 0.0;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) nrm += z[i] * z[i];
+    const double inv = 1.0 / sqrt(nrm);
+#pragma unroll
+    for (int i = 0; i < NP; ++i) z[i] *= inv;
+}
+
+// U <- H_0 H_1 ... H_{n-2} U  (U holds Z on entry); lane c owns column c.
+template <int NP>
+__device__ void wave_backtransform(WaveLds<NP>& S, int n) {
+    constexpr int LD = WaveLds<NP>::LD;
+    const int c = threadIdx.x & 63;
+    if (c < n) {
+        for (int k = n - 2; k >= 0; --k) {
+            const double2 tau = S.tau[k];
+            if (tau.x == 0.0 && tau.y == 0.0) continue;
+            double2 y = c_make(0.0, 0.0);
+            for (int r = k + 1; r < n; ++r) y = c_fmac(S.P[r * LD + k], S.U[r * LD + c], y);
+            const double2 ty = c_mul(tau, y);
+            for (int r = k + 1; r < n; ++r) {
+                const double2 vr = S.P[r * LD + k];
+                S.U[r * LD + c] = c_sub(S.U[r * LD + c], c_mul(vr, ty));
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// M = U^+ v U for one velocity; lane (i = lane/2, half h) returns row i,
+// columns [h NP/2, (h+1) NP/2) of M in M[].  v_il = sum_rho coef_rho T[rho][i][l],
+// coef = e^{i k0 rho} (times i rho for v_x).  W = v U passes through S.P.
+template <int NP>
+__device__ void wave_velocity(WaveLds<NP>& S, int n, int nR0, const double2* __restrict__ T,
+                              const int* __restrict__ r0, bool is_x, double2 (&M)[NP / 2]) {
+    constexpr int LD = WaveLds<NP>::LD;
+    constexpr int HW = NP / 2;
+    const int lane = threadIdx.x & 63;
+    const int i = lane >> 1;
+    const int j0 = (lane & 1) * HW;
+    const long long nn = (long long)n * n;
+    double2 acc[HW];
+#pragma unroll
+    for (int jj = 0; jj < HW; ++jj) acc[jj] = c_make(0.0, 0.0);
+    if (i < n) {
+        for (int l = 0; l < n; ++l) {
+            double2 v = c_make(0.0, 0.0);
+            for (int rho = 0; rho < nR0; ++rho) {
+                double2 cf = S.ph[rho];
+                if (is_x) cf = c_scale((double)r0[rho], c_i(cf));
+                v = c_fma(cf, T[(long long)rho * nn + i * n + l], v);
+            }
+#pragma unroll
+            for (int jj = 0; jj < HW; ++jj) acc[jj] = c_fma(v, S.U[l * LD + j0 + jj], acc[jj]);
+        }
+    }
+    __syncthreads();
+    if (i < n) {
+#pragma unroll
+        for (int jj = 0; jj < HW; ++jj)
+            if (j0 + jj < n) S.P[i * LD + j0 + jj] = acc[jj];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int jj = 0; jj < HW; ++jj) acc[jj] = c_make(0.0, 0.0);
+    if (i < n) {
+        for (int l = 0; l < n; ++l) {
+            const double2 u = S.U[l * LD + i];
+#pragma unroll
+            for (int jj = 0; jj < HW; ++jj)
+                if (j0 + jj < n) acc[jj] = c_fmac(u, S.P[l * LD + j0 + jj], acc[jj]);
+        }
+    }
+#pragma unroll
+    for (int jj = 0; jj < HW; ++jj) M[jj] = acc[jj];
+    __syncthreads();
+}
+
+// Steps 1-3 at one k-point, one wavefront: E (S.E), U (S.U) and the register
+// tiles of A = U^+ v_x U and B = U^+ v_y U.  Returns false on QL non-convergence.
+template <int NP>
+__device__ bool wave_eigen_velocities(WaveLds<NP>& S, const ModelDev& md,
+                                      const double2* __restrict__ T0, const double2* __restrict__ T1,
+                                      const int* __restrict__ r0, int i0, int max_iter,
+                                      double2 (&Ma)[NP / 2], double2 (&Mb)[NP / 2]) {
+    constexpr int LD = WaveLds<NP>::LD;
+    const int lane = threadIdx.x & 63;
+    const int n = md.n;
+    const long long nn = (long long)n * n;
+    if (lane < md.nR0) S.ph[lane] = unit_phase((long long)i0 * r0[lane], md.N0);
+    __syncthreads();
+    for (int e = lane; e < n * n; e += 64) {
+        const int i = e / n, j = e - (e / n) * n;
+        if (i > j) continue;
+        double2 h = c_make(0.0, 0.0);
+        for (int rho = 0; rho < md.nR0; ++rho) h = c_fma(T0[(long long)rho * nn + e], S.ph[rho], h);
+        if (i == j) h.y = 0.0;
+        S.P[i * LD + j] = h;
+        S.P[j * LD + i] = c_conj(h);
+    }
+    __syncthreads();
+    double d_lane, e_lane;
+    wave_tridiag<NP>(S, n, d_lane, e_lane);
+    if (lane < NP) S.de2[lane] = (lane < n) ? c_make(d_lane, e_lane) : c_make(0.0, 0.0);
+    __syncthreads();
+    // Gershgorin interval and the pivot floor of the Sturm sequences
+    const double e_prev = (lane > 0 && lane < n) ? S.de2[lane - 1].y : 0.0;
+    const double rad = (lane < n) ? fabs(e_prev) + fabs(e_lane) : 0.0;
+    const double glo = wave_min(lane < n ? d_lane - rad : 1e300);
+    const double ghi = wave_max(lane < n ? d_lane + rad : -1e300);
+    const double emax = wave_max(lane < n ? fabs(e_lane) : 0.0);
+    const double pivmin = 1e-290 * fmax(1.0, emax * emax);
+    bool ok = true;
+    const double lam2 = wave_bisect<NP>(S, n, glo, ghi, pivmin);
+    const double lam = __shfl(lam2, 2 * lane, 64);  // lane j: eigenvalue j
+    const double lnext = __shfl_down(lam, 1, 64);
+    const double span = fmax(fabs(glo), fabs(ghi));
+    const bool close = (lane < n - 1) && (lnext - lam < 1e-3 * span);
+    // (the debug iteration cap sends every k-point through the iterative path)
+    if (__ballot(close) == 0ull && max_iter > 1) {
+        // isolated eigenvalues: one twisted factorisation per lane
+        if (lane < n) {
+            double z[NP];
+            wave_twisted<NP>(S, n, lam, pivmin, z);
+#pragma unroll
+            for (int i = 0; i < NP; ++i)
+                if (i < n) S.U[i * LD + lane] = c_make(z[i], 0.0);
+            S.E[lane] = lam;
+            if (!isfinite(lam)) ok = false;
+        }
+    } else {
+        // a cluster: implicit QL with accumulated rotations
+        for (int e = lane; e < n * n; e += 64) {
+            const int i = e / n, j = e - (e / n) * n;
+            S.U[i * LD + j] = c_make(i == j ? 1.0 : 0.0, 0.0);
+        }
+        __syncthreads();
+        ok = wave_ql<NP>(S, n, d_lane, e_lane, max_iter);
+        if (lane < n) S.E[lane] = d_lane;
+        if (__ballot(lane < n && !isfinite(d_lane)) != 0ull) ok = false;
+    }
+    if (__ballot(!ok) != 0ull) ok = false;
+    __syncthreads();
+    wave_backtransform<NP>(S, n);
+    wave_velocity<NP>(S, n, md.nR0, T0, r0, true, Ma);
+    wave_velocity<NP>(S, n, md.nR0, T1, r0, false, Mb);
+    return ok;
+}
+
+// ---------------------------------------------------------------------------
+// k_forward_wave: steps 1-4 with one wavefront per workgroup (n <= NP <= 32)
+// ---------------------------------------------------------------------------
+template <int NP>
+__global__ __launch_bounds__(64) void k_forward_wave(FwdLaunch a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    WaveLds<NP>& S = *reinterpret_cast<WaveLds<NP>*>(smem_raw);
+    constexpr int HW = NP / 2;
+    const int lane = threadIdx.x & 63;
+    const double eta2 = a.eta * a.eta;
+    const int max_iter = a.max_sweeps >= kMaxSweeps ? 30 : 1;
+    const double2* tbuf = reinterpret_cast<const double2*>(a.tbuf);
+    for (int item = blockIdx.x; item < a.item_count; item += gridDim.x) {
+        const BlockItem it = a.tb.blocks[a.item_begin + item];
+        const ModelDev md = a.tb.models[it.model];
+        const int n = md.n;
+        const long long nn = (long long)n * n;
+        const double2* T0 = tbuf + it.tbuf_off;
+        const double2* T1 = T0 + (long long)md.nR0 * nn;
+        const int* r0 = a.tb.r0val + md.r0_first;
+        const double* ef = a.e_fermi + md.f_off;
+        double* part = a.partial + (long long)it.slot * a.nF;
+        for (int kk = 0; kk < it.count; ++kk) {
+            double2 Ma[HW], Mb[HW];
+            const bool ok = wave_eigen_velocities<NP>(S, md, T0, T1, r0, it.i0 + kk, max_iter, Ma, Mb);
+            if (!ok && lane == 0) atomicOr(a.status, kStatNoConv);
+            // Omega_i = -2 sum_{j != i} Im(A_ij B_ji) g(E_i - E_j), B_ji = conj(B_ij)
+            const int i = lane >> 1;
+            const int j0 = (lane & 1) * HW;
+            double om = 0.0;
+            if (i < n) {
+                const double ei = S.E[i];
+#pragma unroll
+                for (int jj = 0; jj < HW; ++jj) {
+                    const int j = j0 + jj;
+                    if (j < n && j != i) {
+                        const double de = ei - S.E[j];
+                        const double den = de * de + eta2;
+                        if (den > 0.0) {
+                            const double q = Ma[jj].y * Mb[jj].x - Ma[jj].x * Mb[jj].y;
+                            om += q / den;
+                        }
+                    }
+                }
+            }
+            om += __shfl_xor(om, 1, 64);
+            if (i < n && (lane & 1) == 0) S.Om[i] = -2.0 * om;
+            __syncthreads();
+            for (int j = lane; j < a.nF; j += 64) {
+                const double efj = ef[j];
+                double s = 0.0;
+                for (int b = 0; b < n; ++b) s += occupation(S.E[b], efj, a.kT) * S.Om[b];
+                if (!isfinite(s)) atomicOr(a.status, kStatNonFinite);
+                part[j] = (kk == 0) ? s : part[j] + s;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <int NP>
+static hipError_t launch_forward_wave_t(const FwdLaunch& L, hipStream_t s) {
+    const size_t lds = sizeof(WaveLds<NP>);
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_forward_wave<NP>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    int grid = L.item_count < L.max_groups ? L.item_count : L.max_groups;
+    hipLaunchKernelGGL((k_forward_wave<NP>), dim3(grid), dim3(64), lds, s, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_forward_wave(const FwdLaunch& L, hipStream_t s) {
+    if (L.item_count <= 0) return hipSuccess;
+    switch (L.np) {
+        case 8:
+            return launch_forward_wave_t<8>(L, s);
+        case 16:
+            return launch_forward_wave_t<16>(L, s);
+        case 32:
+            return launch_forward_wave_t<32>(L, s);
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace kubo
