@@ -72,6 +72,10 @@ def main(argv=None):
     ap.add_argument("--cpu-sample", type=int, default=4096,
                     help="k-points the CPU oracle is timed on (0 skips it)")
     ap.add_argument("--k-block", type=int, default=0, help="override the k-block of the plan")
+    ap.add_argument("--threads", type=int, default=0,
+                    help="per-k kernel: 64 = one wavefront, 256 = one workgroup (0 = default)")
+    ap.add_argument("--adjoint-steps", type=int, default=1,
+                    help="timed backward passes for the adjoint/forward ratio (0 skips)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -89,7 +93,9 @@ def main(argv=None):
     ef = fermi_levels(cfg, wl)
     dev = "cuda:0"
     torch.cuda.set_device(0)
-    tiles = [(model.n, 0, args.k_block)] if args.k_block > 0 else None
+    tiles = None
+    if args.k_block > 0 or args.threads > 0:
+        tiles = [(model.n, args.threads, args.k_block if args.k_block > 0 else 32)]
     plan = kubo.Plan([model], grid=wl.grid, n_fermi=wl.n_fermi, flags=kubo.KUBO_F_TIMING,
                      tiles=tiles, device=dev)
     t = kubo.to_device_t([model], dev)
@@ -146,6 +152,26 @@ def main(argv=None):
                      "launches_per_step": launches / args.steps},
         "sigma_checksum": float(sigma.sum().item()),
     }
+    if args.adjoint_steps > 0:
+        # adjoint of sum_j sbar_j sigma_j over the same grid (all hoppings), same stream
+        sbar = torch.ones(1, wl.n_fermi, dtype=torch.float64, device=dev)
+        grad = torch.empty_like(t)
+        plan.backward(t, efd, wl.eta, wl.kT, sbar, out=grad)
+        torch.cuda.synchronize()
+        plan.kernel_time(1, reset=True)
+        start.record(stream)
+        for _ in range(args.adjoint_steps):
+            plan.backward(t, efd, wl.eta, wl.kT, sbar, out=grad)
+        stop.record(stream)
+        torch.cuda.synchronize()
+        st = plan.device_status()
+        if st != kubo.KUBO_OK:
+            raise SystemExit(f"device status (backward): {kubo.kubo_status_string(st)}")
+        bms = start.elapsed_time(stop) / args.adjoint_steps
+        out["adjoint"] = {"ms_per_step": bms, "k_points_per_s": plan.total_k / (bms / 1e3),
+                          "adjoint_forward_ratio": bms / (ms / args.steps),
+                          "kernel_ms_per_step": plan.kernel_time(1)[0] / args.adjoint_steps,
+                          "grad_checksum": float(grad.abs().sum().item())}
     if args.cpu_sample > 0:
         out["cpu_baseline"] = cpu_baseline(model, wl, ef[0], args.cpu_sample)
     print(json.dumps(out), flush=True)

@@ -74,7 +74,8 @@ typedef struct {
 /* Per-orbital-count launch shape; the autotuner writes these. */
 typedef struct {
     int32_t n_orb;        /* the models with this n use the entry */
-    int32_t threads;      /* threads per workgroup: 64, 128, 256 or 512 */
+    int32_t threads;      /* 0 = default; 64 = one wavefront per k-point (n <= 32 only);
+                             256 = one 256-thread workgroup per k-point */
     int32_t k_block;      /* k-points per work item (a piece of one kx pencil), >= 1 */
     int32_t reserved;     /* must be 0 */
 } kubo_tile;

@@ -23,13 +23,15 @@ namespace {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-// Padded size classes with an instantiated forward kernel, and their default
-// workgroup sizes.
+// Size classes of the forward per-k kernel: one wavefront per k-point with the
+// matrices padded to np (n <= 32), or one workgroup per k-point with the
+// matrices in workspace scratch (np = 128 marks that class).  The adjoint
+// always uses the workgroup kernel.
 struct ClassInfo {
     int np;
-    int nt;
+    bool wave;
 };
-const ClassInfo kClasses[] = {{8, 64}, {16, 128}, {32, 256}};
+const ClassInfo kClasses[] = {{8, true}, {16, true}, {32, true}, {128, false}};
 constexpr int kNumClasses = sizeof(kClasses) / sizeof(kClasses[0]);
 
 int class_of(int n) {
@@ -92,6 +94,9 @@ struct kubo_plan_s {
     long long t_elems = 0;  // complex elements of t (all models)
     // workspace layout
     size_t off_tables = 0, off_tp = 0, off_tbuf = 0, off_pbuf = 0, off_partial = 0, total = 0;
+    size_t off_scratch = 0;
+    long long slot_elems = 0;
+    int wg_groups = 512;
     std::vector<unsigned char> blob;
     size_t tab_off[11] = {0};
     const void* uploaded_ws = nullptr;
@@ -202,7 +207,8 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
         int kblock = std::min(d.grid[0], 32);
         auto ti = tile_of.find(d.n_orb);
         if (ti != tile_of.end()) kblock = std::min(d.grid[0], ti->second.k_block);
-        const int cls = class_of(d.n_orb);
+        int cls = class_of(d.n_orb);
+        if (ti != tile_of.end() && ti->second.threads == 256) cls = kNumClasses - 1;
         md.slot_first = slot;
         const long long nn = (long long)d.n_orb * d.n_orb;
         const size_t mat_bytes = (size_t)2 * md.nR0 * nn * 16;
@@ -316,6 +322,20 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
     off = align_up(off + max_p);
     P->off_partial = off;
     off = align_up(off + (size_t)P->n_slots * nF * 8);
+    {
+        int nmax = 1;
+        for (const auto& md : P->models) nmax = std::max(nmax, md.n);
+        P->slot_elems = wg_slot_elems(nmax);
+        int most = 1;
+        for (const Chunk& c : P->chunks) {
+            int cnt = 0;
+            for (int k = 0; k < kNumClasses; ++k) cnt = std::max(cnt, c.cls[k].count);
+            most = std::max(most, cnt);
+        }
+        P->wg_groups = std::min(P->wg_groups, most);
+    }
+    P->off_scratch = off;
+    off = align_up(off + (size_t)P->wg_groups * (size_t)P->slot_elems * 16);
     P->total = off;
     return KUBO_OK;
 }
@@ -330,9 +350,8 @@ kubo_status validate(const kubo_model_desc* models, int n_models, int nF, uint32
         const kubo_tile& t = tiles[i];
         if (t.n_orb < 1 || t.n_orb > kMaxOrb || t.k_block < 1 || t.reserved != 0)
             return KUBO_E_INVALID;
-        if (t.threads != 0 && t.threads != 64 && t.threads != 128 && t.threads != 256 &&
-            t.threads != 512)
-            return KUBO_E_INVALID;
+        if (t.threads != 0 && t.threads != 64 && t.threads != 256) return KUBO_E_INVALID;
+        if (t.threads == 64 && t.n_orb > 32) return KUBO_E_INVALID;
     }
     bool unsupported = false;
     for (int m = 0; m < n_models; ++m) {
@@ -419,28 +438,51 @@ kubo_status enqueue_forward(kubo_plan_s* P, const double* t, const double* ef, d
     double* tp = reinterpret_cast<double*>(ws + P->off_tp);
     double* tbuf = reinterpret_cast<double*>(ws + P->off_tbuf);
     double* partial = reinterpret_cast<double*>(ws + P->off_partial);
+    double* scratch = reinterpret_cast<double*>(ws + P->off_scratch);
+    const int max_iter = (P->flags & KUBO_F_DEBUG_SWEEPCAP) ? 1 : kMaxSweeps;
     HIP_TRY(launch_clear(status, s));
     HIP_TRY(launch_hermproj(tb, P->n_models, P->t_elems, t, tp, s));
     for (const Chunk& c : P->chunks) {
         HIP_TRY(launch_pencil(tb, c.pencil_begin, c.pencil_count, tp, tbuf, s));
         for (int k = 0; k < kNumClasses; ++k) {
             if (c.cls[k].count == 0) continue;
-            FwdLaunch L;
-            L.tb = tb;
-            L.tbuf = tbuf;
-            L.e_fermi = ef;
-            L.partial = partial;
-            L.status = status;
-            L.eta = eta;
-            L.kT = kT;
-            L.nF = P->nF;
-            L.max_sweeps = (P->flags & KUBO_F_DEBUG_SWEEPCAP) ? 1 : kMaxSweeps;
-            L.item_begin = c.cls[k].begin;
-            L.item_count = c.cls[k].count;
-            L.np = kClasses[k].np;
-            L.max_groups = P->max_groups;
             TimedScope ts(P, s, 0, c.cls_kpts[k]);
-            HIP_TRY(launch_forward_wave(L, s));
+            if (kClasses[k].wave) {
+                FwdLaunch L;
+                L.tb = tb;
+                L.tbuf = tbuf;
+                L.e_fermi = ef;
+                L.partial = partial;
+                L.status = status;
+                L.eta = eta;
+                L.kT = kT;
+                L.nF = P->nF;
+                L.max_sweeps = max_iter;
+                L.item_begin = c.cls[k].begin;
+                L.item_count = c.cls[k].count;
+                L.np = kClasses[k].np;
+                L.max_groups = P->max_groups;
+                HIP_TRY(launch_forward_wave(L, s));
+            } else {
+                WgLaunch L{};
+                L.tb = tb;
+                L.tbuf = tbuf;
+                L.pbuf = nullptr;
+                L.e_fermi = ef;
+                L.sbar = nullptr;
+                L.partial = partial;
+                L.status = status;
+                L.scratch = scratch;
+                L.slot_elems = P->slot_elems;
+                L.eta = eta;
+                L.kT = kT;
+                L.nF = P->nF;
+                L.max_iter = max_iter;
+                L.item_begin = c.cls[k].begin;
+                L.item_count = c.cls[k].count;
+                L.max_groups = P->wg_groups;
+                HIP_TRY(launch_forward_wg(L, s));
+            }
             ts.finish();
         }
     }
@@ -456,6 +498,8 @@ kubo_status enqueue_backward(kubo_plan_s* P, const double* t, const double* ef, 
     double* tp = reinterpret_cast<double*>(ws + P->off_tp);
     double* tbuf = reinterpret_cast<double*>(ws + P->off_tbuf);
     double* pbuf = reinterpret_cast<double*>(ws + P->off_pbuf);
+    double* scratch = reinterpret_cast<double*>(ws + P->off_scratch);
+    const int max_iter = (P->flags & KUBO_F_DEBUG_SWEEPCAP) ? 1 : kMaxSweeps;
     HIP_TRY(launch_clear(status, s));
     HIP_TRY(launch_hermproj(tb, P->n_models, P->t_elems, t, tp, s));
     HIP_TRY(launch_zero(grad, 2 * P->t_elems, s));
@@ -463,23 +507,25 @@ kubo_status enqueue_backward(kubo_plan_s* P, const double* t, const double* ef, 
         HIP_TRY(launch_pencil(tb, c.pencil_begin, c.pencil_count, tp, tbuf, s));
         for (int k = 0; k < kNumClasses; ++k) {
             if (c.cls[k].count == 0) continue;
-            AdjLaunch L;
+            WgLaunch L{};
             L.tb = tb;
             L.tbuf = tbuf;
             L.pbuf = pbuf;
             L.e_fermi = ef;
             L.sbar = sbar;
+            L.partial = nullptr;
             L.status = status;
+            L.scratch = scratch;
+            L.slot_elems = P->slot_elems;
             L.eta = eta;
             L.kT = kT;
             L.nF = P->nF;
-            L.max_sweeps = (P->flags & KUBO_F_DEBUG_SWEEPCAP) ? 1 : kMaxSweeps;
+            L.max_iter = max_iter;
             L.item_begin = c.cls[k].begin;
             L.item_count = c.cls[k].count;
-            L.np = kClasses[k].np;
-            L.max_groups = P->max_groups;
+            L.max_groups = P->wg_groups;
             TimedScope ts(P, s, 1, c.cls_kpts[k]);
-            HIP_TRY(launch_adjoint(L, s));
+            HIP_TRY(launch_adjoint_wg(L, s));
             ts.finish();
         }
         HIP_TRY(launch_gacc(tb, tb.granges, c.grange_begin, c.grange_count, P->max_nR, P->max_nn,

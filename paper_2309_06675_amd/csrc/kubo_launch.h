@@ -21,20 +21,26 @@ struct FwdLaunch {
     int max_groups;  // persistent grid size cap
 };
 
-struct AdjLaunch {
+struct WgLaunch {
     Tables tb;
     const double* tbuf;
     double* pbuf;
     const double* e_fermi;
     const double* sbar;
+    double* partial;
     unsigned* status;
+    double* scratch;       // max_groups slots of slot_elems complex elements
+    long long slot_elems;
     double eta, kT;
     int nF;
-    int max_sweeps;
+    int max_iter;
     int item_begin, item_count;
-    int np;
     int max_groups;
 };
+
+long long wg_slot_elems(int nmax);
+hipError_t launch_forward_wg(const WgLaunch& L, hipStream_t s);
+hipError_t launch_adjoint_wg(const WgLaunch& L, hipStream_t s);
 
 hipError_t launch_clear(unsigned* status, hipStream_t s);
 hipError_t launch_zero(double* p, long long count, hipStream_t s);
@@ -42,9 +48,7 @@ hipError_t launch_hermproj(const Tables& tb, int n_models, long long total, cons
                            double* tp, hipStream_t s);
 hipError_t launch_pencil(const Tables& tb, int item_begin, int item_count, const double* tp,
                          double* tbuf, hipStream_t s);
-hipError_t launch_forward(const FwdLaunch& L, hipStream_t s);
 hipError_t launch_forward_wave(const FwdLaunch& L, hipStream_t s);
-hipError_t launch_adjoint(const AdjLaunch& L, hipStream_t s);
 hipError_t launch_gacc(const Tables& tb, const GaccRange* ranges, int range_begin, int range_count,
                        int max_nR, long long max_nn, const double* pbuf, double* grad,
                        hipStream_t s);

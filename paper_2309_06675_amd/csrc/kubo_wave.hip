@@ -282,7 +282,7 @@ __device__ double wave_bisect(const WaveLds<NP>& S, int n, double glo, double gh
 // twist index r = argmin |dp_r + dm_r - (d_r - lam)|, then z_r = 1 and the two
 // one-sided recurrences.  Returns the normalised vector in z[0..NP).
 template <int NP>
-__device__ void wave_twisted(const WaveLds<NP>& S, int n, double lam, double pivmin,
+__device__ void wave_twisted(const WaveLds<NP>& S, int n, double& lam, double pivmin,
                              double (&z)[NP]) {
     double dp[NP], dm[NP];
     {
@@ -309,13 +309,14 @@ __device__ void wave_twisted(const WaveLds<NP>& S, int n, double lam, double piv
         }
     }
     int r = 0;
-    double best = 1e308;
+    double best = 1e308, gam = 0.0;
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
         if (i < n) {
-            const double g = fabs(dp[i] + dm[i] - (S.de2[i].x - lam));
-            if (g < best) {
-                best = g;
+            const double g = dp[i] + dm[i] - (S.de2[i].x - lam);
+            if (fabs(g) < best) {
+                best = fabs(g);
+                gam = g;
                 r = i;
             }
         }
@@ -339,6 +340,8 @@ __device__ void wave_twisted(const WaveLds<NP>& S, int n, double lam, double piv
     double nrm = 0.0;
 #pragma unroll
     for (int i = 0; i < NP; ++i) nrm += z[i] * z[i];
+    // (T - lam) z = gam e_r with z_r = 1: the Rayleigh quotient is lam + gam / |z|^2
+    lam += gam / nrm;
     const double inv = 1.0 / sqrt(nrm);
 #pragma unroll
     for (int i = 0; i < NP; ++i) z[i] *= inv;
@@ -459,12 +462,13 @@ __device__ bool wave_eigen_velocities(WaveLds<NP>& S, const ModelDev& md,
         // isolated eigenvalues: one twisted factorisation per lane
         if (lane < n) {
             double z[NP];
-            wave_twisted<NP>(S, n, lam, pivmin, z);
+            double lam_j = lam;
+            wave_twisted<NP>(S, n, lam_j, pivmin, z);
 #pragma unroll
             for (int i = 0; i < NP; ++i)
                 if (i < n) S.U[i * LD + lane] = c_make(z[i], 0.0);
-            S.E[lane] = lam;
-            if (!isfinite(lam)) ok = false;
+            S.E[lane] = lam_j;
+            if (!isfinite(lam_j)) ok = false;
         }
     } else {
         // a cluster: implicit QL with accumulated rotations

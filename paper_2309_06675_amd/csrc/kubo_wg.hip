@@ -1,0 +1,735 @@
+// kubo_wg.hip -- one workgroup (256 threads) per k-point for 32 < n <= 128,
+// forward and adjoint.
+//
+// Same method as the one-wavefront path (Householder reduction to a real
+// tridiagonal matrix, Sturm-count multisection for the eigenvalues, twisted
+// factorisations for the eigenvectors with an implicit-QL path for clustered
+// spectra, back-transformation, U^+ v U), but the n x n matrices of the k-point
+// being processed live in a per-workgroup slice of the workspace (it stays in
+// L2 / the last-level cache) instead of LDS, which cannot hold them at n = 128.
+// Products of matrices go through 32 x 32 LDS tiles.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "kubo_cplx.h"
+#include "kubo_internal.h"
+#include "kubo_launch.h"
+
+namespace kubo {
+
+constexpr int kWgThreads = 256;
+constexpr int kWgMaxN = 128;
+constexpr int kTile = 32;
+
+struct WgLds {
+    double2 xv[kWgMaxN];
+    double2 vv[kWgMaxN];
+    double2 wv[kWgMaxN];
+    double2 tau[kWgMaxN];
+    double d[kWgMaxN];
+    double e[kWgMaxN];
+    double lam[kWgMaxN];
+    double cs[2 * kWgMaxN];
+    double en[kWgMaxN];
+    double dn[kWgMaxN];
+    double E[kWgMaxN];
+    double Om[kWgMaxN];
+    double phi[kWgMaxN];
+    double dphi[kWgMaxN];
+    double2 ph[16];
+    double red[2 * (kWgThreads / 64)];
+    int flag;
+    double2 ta[kTile * (kTile + 1)];
+    double2 tb[kTile * (kTile + 1)];
+};
+
+// Per-workgroup scratch: seven n_max x n_max complex matrices.
+struct WgScratch {
+    double2* P;    // H, then Householder vectors; adjoint: product scratch
+    double2* U;    // Z, then U
+    double2* VX;   // v_x, then A = U^+ v_x U; adjoint: vbar_y
+    double2* VY;   // v_y, then B = U^+ v_y U; adjoint: vbar_x
+    double2* W;    // product scratch; adjoint: Hbar', then Hbar
+    double* DPM;   // pivots of the twisted factorisations (2 n^2 doubles)
+    double* K;     // adjoint: K_mn (n^2 doubles)
+};
+
+__device__ __forceinline__ WgScratch wg_scratch(double2* base, long long slot_elems, int slot) {
+    const long long m2 = slot_elems / 7;
+    double2* b = base + (long long)slot * slot_elems;
+    WgScratch s;
+    s.P = b;
+    s.U = b + m2;
+    s.VX = b + 2 * m2;
+    s.VY = b + 3 * m2;
+    s.W = b + 4 * m2;
+    s.DPM = reinterpret_cast<double*>(b + 5 * m2);
+    s.K = reinterpret_cast<double*>(b + 6 * m2);
+    return s;
+}
+
+// Workgroup sum of one double (all threads get the result).
+__device__ __forceinline__ double wg_sum(double v, double* red) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < kWgThreads / 64; ++w) s += red[w];
+    __syncthreads();
+    return s;
+}
+__device__ __forceinline__ double wg_min(double v, double* red) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = red[0];
+    for (int w = 1; w < kWgThreads / 64; ++w) s = fmin(s, red[w]);
+    __syncthreads();
+    return s;
+}
+__device__ __forceinline__ double wg_max(double v, double* red) {
+    return -wg_min(-v, red);
+}
+
+// ---------------------------------------------------------------------------
+// step 1: H (Hermitian, upper triangle mirrored), v_x, v_y into the scratch
+// ---------------------------------------------------------------------------
+__device__ void wg_build(WgLds& S, const WgScratch& X, const ModelDev& md,
+                         const double2* __restrict__ T0, const double2* __restrict__ T1,
+                         const int* __restrict__ r0, int i0) {
+    const int n = md.n;
+    const long long nn = (long long)n * n;
+    if (threadIdx.x < md.nR0) S.ph[threadIdx.x] = unit_phase((long long)i0 * r0[threadIdx.x], md.N0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * n; e += kWgThreads) {
+        const int i = e / n, j = e - (e / n) * n;
+        double2 h = c_make(0.0, 0.0), x = h, y = h;
+        for (int rho = 0; rho < md.nR0; ++rho) {
+            const double2 p0 = c_mul(T0[(long long)rho * nn + e], S.ph[rho]);
+            h = c_add(h, p0);
+            x = c_add(x, c_scale((double)r0[rho], c_i(p0)));
+            y = c_fma(T1[(long long)rho * nn + e], S.ph[rho], y);
+        }
+        X.VX[e] = x;
+        X.VY[e] = y;
+        if (i <= j) {
+            if (i == j) h.y = 0.0;
+            X.P[i * n + j] = h;
+            X.P[j * n + i] = c_conj(h);
+        }
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// step 2a: Householder reduction of P to real tridiagonal (S.d, S.e)
+// ---------------------------------------------------------------------------
+__device__ void wg_tridiag(WgLds& S, double2* __restrict__ P, int n) {
+    const int tid = threadIdx.x;
+    for (int k = 0; k < n - 1; ++k) {
+        const int m = n - k - 1;
+        for (int r = k + 1 + tid; r < n; r += kWgThreads) S.xv[r] = P[r * n + k];
+        __syncthreads();
+        double part = 0.0;
+        for (int r = k + 2 + tid; r < n; r += kWgThreads) part += S.xv[r].x * S.xv[r].x + S.xv[r].y * S.xv[r].y;
+        const double xn2 = wg_sum(part, S.red);
+        const double2 alpha = S.xv[k + 1];
+        double beta;
+        double2 tau, scal;
+        if (xn2 == 0.0 && alpha.y == 0.0) {
+            beta = alpha.x;
+            tau = c_make(0.0, 0.0);
+            scal = c_make(0.0, 0.0);
+        } else {
+            const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn2);
+            beta = -copysign(nrm, alpha.x);
+            tau = c_make((beta - alpha.x) / beta, -alpha.y / beta);
+            const double ar = alpha.x - beta, ai = alpha.y;
+            const double den = 1.0 / (ar * ar + ai * ai);
+            scal = c_make(ar * den, -ai * den);
+        }
+        if (tid == 0) {
+            S.d[k] = P[k * n + k].x;
+            S.e[k] = beta;
+            S.tau[k] = tau;
+        }
+        for (int r = k + 1 + tid; r < n; r += kWgThreads) {
+            const double2 v = (r == k + 1) ? c_make(1.0, 0.0) : c_mul(S.xv[r], scal);
+            S.vv[r] = v;
+            P[r * n + k] = v;
+        }
+        __syncthreads();
+        if (tau.x == 0.0 && tau.y == 0.0) continue;
+        // p = A22 v: rows split over thread groups, columns over the group's lanes
+        for (int r = k + 1 + tid / 2; r < n; r += kWgThreads / 2) {
+            double2 p = c_make(0.0, 0.0);
+            for (int c = k + 1 + (tid & 1); c < n; c += 2) p = c_fma(P[r * n + c], S.vv[c], p);
+            p.x += __shfl_xor(p.x, 1, 64);
+            p.y += __shfl_xor(p.y, 1, 64);
+            if ((tid & 1) == 0) S.wv[r] = p;
+        }
+        __syncthreads();
+        double mpart = 0.0;
+        for (int r = k + 1 + tid; r < n; r += kWgThreads) mpart += S.vv[r].x * S.wv[r].x + S.vv[r].y * S.wv[r].y;
+        const double mu = wg_sum(mpart, S.red);
+        const double t2 = 0.5 * (tau.x * tau.x + tau.y * tau.y) * mu;
+        for (int r = k + 1 + tid; r < n; r += kWgThreads)
+            S.wv[r] = c_sub(c_mul(tau, S.wv[r]), c_scale(t2, S.vv[r]));
+        __syncthreads();
+        for (int e = tid; e < m * m; e += kWgThreads) {
+            const int r = k + 1 + e / m, c = k + 1 + (e - (e / m) * m);
+            double2 a = P[r * n + c];
+            a = c_sub(a, c_add(c_mulc(S.vv[r], S.wv[c]), c_mulc(S.wv[r], S.vv[c])));
+            P[r * n + c] = a;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        S.d[n - 1] = P[(n - 1) * n + (n - 1)].x;
+        S.e[n - 1] = 0.0;
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// step 2b: eigenvalues by Sturm-count multisection (S.lam ascending)
+// ---------------------------------------------------------------------------
+__device__ void wg_bisect(WgLds& S, int n, double& pivmin_out, double& span_out) {
+    const int tid = threadIdx.x;
+    double lo_i = 1e300, hi_i = -1e300, emax = 0.0;
+    for (int i = tid; i < n; i += kWgThreads) {
+        const double rad = fabs(S.e[i]) + (i > 0 ? fabs(S.e[i - 1]) : 0.0);
+        lo_i = fmin(lo_i, S.d[i] - rad);
+        hi_i = fmax(hi_i, S.d[i] + rad);
+        emax = fmax(emax, fabs(S.e[i]));
+    }
+    const double glo = wg_min(lo_i, S.red);
+    const double ghi = wg_max(hi_i, S.red);
+    const double em = wg_max(emax, S.red);
+    const double pivmin = 1e-290 * fmax(1.0, em * em);
+    pivmin_out = pivmin;
+    span_out = fmax(fabs(glo), fabs(ghi));
+    int np2 = 1;
+    while (np2 < n) np2 <<= 1;
+    const int tpe = kWgThreads / np2;  // threads per eigenvalue (>= 2)
+    const int j = tid / tpe, q = tid - (tid / tpe) * tpe;
+    const double tol = 4.0 * 2.220446049250313e-16 * span_out + 1e-300;
+    int steps = 0;
+    for (double w = ghi - glo; w > tol && steps < 120; w /= (double)(tpe + 1)) ++steps;
+    double lo = glo, hi = ghi;
+    for (int it = 0; it < steps; ++it) {
+        const double h = (hi - lo) / (double)(tpe + 1);
+        const double x = lo + h * (double)(q + 1);
+        int cnt = 0;
+        double qv = 1.0, e2prev = 0.0;
+        for (int i = 0; i < n; ++i) {
+            double rq = __builtin_amdgcn_rcp(qv);
+            rq = fma(rq, fma(-qv, rq, 1.0), rq);
+            double qi = (S.d[i] - x) - e2prev * rq;
+            if (fabs(qi) < pivmin) qi = -pivmin;
+            cnt += (qi < 0.0) ? 1 : 0;
+            qv = qi;
+            e2prev = S.e[i] * S.e[i];
+        }
+        // first point whose count exceeds j decides the new interval
+        int first = tpe;  // index of the first point with count > j
+        for (int p = 0; p < tpe; ++p) {
+            const int cp = __shfl(cnt, (tid & 63) - q + p, 64);
+            if (cp > j && first == tpe) first = p;
+        }
+        const double nlo = lo + h * (double)first;
+        const double nhi = (first == tpe) ? hi : lo + h * (double)(first + 1);
+        lo = nlo;
+        hi = nhi;
+    }
+    if (q == 0 && j < n) S.lam[j] = 0.5 * (lo + hi);
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// step 2c: eigenvectors of T by twisted factorisations, Z -> U (real parts)
+// thread j owns eigenvector j; pivots go to DPM in [i][j] order (coalesced)
+// ---------------------------------------------------------------------------
+__device__ void wg_twisted(WgLds& S, const WgScratch& X, int n, double pivmin) {
+    const int j = threadIdx.x;
+    const long long nn = (long long)n * n;
+    if (j < n) {
+        const double lam = S.lam[j];
+        double* dp = X.DPM;
+        double* dm = X.DPM + nn;
+        double qv = 1.0, e2prev = 0.0;
+        for (int i = 0; i < n; ++i) {
+            double qi = (S.d[i] - lam) - e2prev / qv;
+            if (fabs(qi) < pivmin) qi = -pivmin;
+            dp[(long long)i * n + j] = qi;
+            qv = qi;
+            e2prev = S.e[i] * S.e[i];
+        }
+        qv = 1.0;
+        int r = 0;
+        double best = 1e308, gam = 0.0;
+        for (int i = n - 1; i >= 0; --i) {
+            double qi = (S.d[i] - lam) - ((i < n - 1) ? S.e[i] * S.e[i] / qv : 0.0);
+            if (fabs(qi) < pivmin) qi = -pivmin;
+            dm[(long long)i * n + j] = qi;
+            qv = qi;
+            const double g = dp[(long long)i * n + j] + qi - (S.d[i] - lam);
+            if (fabs(g) < best) {
+                best = fabs(g);
+                gam = g;
+                r = i;
+            }
+        }
+        double nrm = 1.0;
+        X.U[(long long)r * n + j] = c_make(1.0, 0.0);
+        double z = 1.0;
+        for (int i = r - 1; i >= 0; --i) {
+            z = -(S.e[i] / dp[(long long)i * n + j]) * z;
+            X.U[(long long)i * n + j] = c_make(z, 0.0);
+            nrm += z * z;
+        }
+        z = 1.0;
+        for (int i = r + 1; i < n; ++i) {
+            z = -(S.e[i - 1] / dm[(long long)i * n + j]) * z;
+            X.U[(long long)i * n + j] = c_make(z, 0.0);
+            nrm += z * z;
+        }
+        const double inv = 1.0 / sqrt(nrm);
+        for (int i = 0; i < n; ++i) X.U[(long long)i * n + j].x *= inv;
+        // (T - lam) z = gam e_r with z_r = 1: Rayleigh-quotient correction
+        S.E[j] = lam + gam / nrm;
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// step 2c': implicit QL with accumulated rotations (clustered spectra)
+// every thread follows the same scalar chain (d, e in LDS); thread r owns row r of Z
+// ---------------------------------------------------------------------------
+__device__ bool wg_ql(WgLds& S, double2* __restrict__ Z, int n, int max_iter) {
+    const int tid = threadIdx.x;
+    for (int e = tid; e < n * n; e += kWgThreads) {
+        const int i = e / n, j = e - (e / n) * n;
+        Z[e] = c_make(i == j ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+    bool ok = true;
+    double f = 0.0, tst1 = 0.0;
+    for (int l = 0; l < n && ok; ++l) {
+        int iter = 0;
+        tst1 = fmax(tst1, fabs(S.d[l]) + fabs(S.e[l]));
+        for (;;) {
+            int m = l;
+            while (m < n - 1 && !(tst1 + fabs(S.e[m]) == tst1)) ++m;
+            if (m == l) break;
+            if (++iter > max_iter || !isfinite(tst1)) {
+                ok = false;
+                break;
+            }
+            const double g0 = S.d[l], el = S.e[l];
+            double p = (S.d[l + 1] - g0) / (2.0 * el);
+            double r = sqrt(p * p + 1.0);
+            const double pr = p + copysign(r, p);
+            const double new_dl = el / pr, dl1 = el * pr;
+            double h = g0 - new_dl;
+            __syncthreads();
+            for (int i = l + 2 + tid; i < n; i += kWgThreads) S.d[i] -= h;
+            if (tid == 0) {
+                S.d[l] = new_dl;
+                S.d[l + 1] = dl1;
+            }
+            f += h;
+            __syncthreads();
+            p = S.d[m];
+            double c = 1.0, c2 = 1.0, c3 = 1.0, s = 0.0, s2 = 0.0;
+            const double el1 = S.e[l + 1];
+            // the chain: every thread computes it from the unmodified d, e;
+            // thread 0 records the new values aside and the rotations
+            for (int i = m - 1; i >= l; --i) {
+                c3 = c2;
+                c2 = c;
+                s2 = s;
+                const double ei = S.e[i], di = S.d[i];
+                const double g = c * ei;
+                h = c * p;
+                r = sqrt(p * p + ei * ei);
+                const double e_ip1 = s * r;
+                const double inv = 1.0 / r;
+                s = ei * inv;
+                c = p * inv;
+                p = c * di - s * g;
+                const double d_ip1 = h + s * (c * g + s * di);
+                if (tid == 0) {
+                    S.en[i + 1] = e_ip1;
+                    S.dn[i + 1] = d_ip1;
+                    S.cs[2 * i] = c;
+                    S.cs[2 * i + 1] = s;
+                }
+            }
+            __syncthreads();
+            for (int i = l + 1 + tid; i <= m; i += kWgThreads) {
+                S.e[i] = S.en[i];
+                S.d[i] = S.dn[i];
+            }
+            if (tid == 0) {
+                const double pp = -s * s2 * c3 * el1 * el / dl1;
+                S.e[l] = s * pp;
+                S.d[l] = c * pp;
+            }
+            __syncthreads();
+            for (int row = tid; row < n; row += kWgThreads) {
+                double carry = Z[row * n + m].x;
+                for (int i = m - 1; i >= l; --i) {
+                    const double ci = S.cs[2 * i], si = S.cs[2 * i + 1];
+                    const double zi = Z[row * n + i].x;
+                    Z[row * n + i + 1].x = si * zi + ci * carry;
+                    carry = ci * zi - si * carry;
+                }
+                Z[row * n + l].x = carry;
+            }
+            __syncthreads();
+        }
+        __syncthreads();
+        if (tid == 0) S.d[l] += f;
+        __syncthreads();
+    }
+    for (int i = tid; i < n; i += kWgThreads) {
+        S.E[i] = S.d[i];
+        if (!isfinite(S.d[i])) ok = false;
+    }
+    __syncthreads();
+    return ok;
+}
+
+// ---------------------------------------------------------------------------
+// step 2d: U <- H_0 ... H_{n-2} U (thread c owns column c)
+// ---------------------------------------------------------------------------
+__device__ void wg_backtransform(WgLds& S, const double2* __restrict__ P, double2* __restrict__ U,
+                                 int n) {
+    const int c = threadIdx.x;
+    if (c < n) {
+        for (int k = n - 2; k >= 0; --k) {
+            const double2 tau = S.tau[k];
+            if (tau.x == 0.0 && tau.y == 0.0) continue;
+            double2 y = c_make(0.0, 0.0);
+            for (int r = k + 1; r < n; ++r) y = c_fmac(P[r * n + k], U[r * n + c], y);
+            const double2 ty = c_mul(tau, y);
+            for (int r = k + 1; r < n; ++r) U[r * n + c] = c_sub(U[r * n + c], c_mul(P[r * n + k], ty));
+        }
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// C = LA * LB through 32 x 32 LDS tiles; LA(i, k) and LB(k, j) return the
+// operand elements (so transposes, conjugates and elementwise factors are free)
+// ---------------------------------------------------------------------------
+template <class FA, class FB>
+__device__ void wg_gemm(WgLds& S, double2* __restrict__ C, int n, FA LA, FB LB) {
+    const int tid = threadIdx.x;
+    const int ti = tid >> 4, tj = tid & 15;  // 2 x 2 outputs per thread
+    const int nt = (n + kTile - 1) / kTile;
+    for (int bi = 0; bi < nt; ++bi)
+        for (int bj = 0; bj < nt; ++bj) {
+            double2 acc[2][2];
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) acc[a][b] = c_make(0.0, 0.0);
+            for (int bk = 0; bk < nt; ++bk) {
+                for (int e = tid; e < kTile * kTile; e += kWgThreads) {
+                    const int r = e / kTile, c = e - (e / kTile) * kTile;
+                    const int gi = bi * kTile + r, gk = bk * kTile + c;
+                    S.ta[r * (kTile + 1) + c] = (gi < n && gk < n) ? LA(gi, gk) : c_make(0.0, 0.0);
+                    const int gk2 = bk * kTile + r, gj = bj * kTile + c;
+                    S.tb[r * (kTile + 1) + c] = (gk2 < n && gj < n) ? LB(gk2, gj) : c_make(0.0, 0.0);
+                }
+                __syncthreads();
+                for (int kk = 0; kk < kTile; ++kk) {
+                    const double2 a0 = S.ta[(2 * ti) * (kTile + 1) + kk];
+                    const double2 a1 = S.ta[(2 * ti + 1) * (kTile + 1) + kk];
+                    const double2 b0 = S.tb[kk * (kTile + 1) + 2 * tj];
+                    const double2 b1 = S.tb[kk * (kTile + 1) + 2 * tj + 1];
+                    acc[0][0] = c_fma(a0, b0, acc[0][0]);
+                    acc[0][1] = c_fma(a0, b1, acc[0][1]);
+                    acc[1][0] = c_fma(a1, b0, acc[1][0]);
+                    acc[1][1] = c_fma(a1, b1, acc[1][1]);
+                }
+                __syncthreads();
+            }
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) {
+                    const int gi = bi * kTile + 2 * ti + a, gj = bj * kTile + 2 * tj + b;
+                    if (gi < n && gj < n) C[gi * n + gj] = acc[a][b];
+                }
+        }
+    __syncthreads();
+}
+
+// Steps 1-3: E (S.E), U, and A = U^+ v_x U in X.VX, B = U^+ v_y U in X.VY.
+__device__ bool wg_eigen_velocities(WgLds& S, const WgScratch& X, const ModelDev& md,
+                                    const double2* __restrict__ T0, const double2* __restrict__ T1,
+                                    const int* __restrict__ r0, int i0, int max_iter) {
+    const int n = md.n;
+    wg_build(S, X, md, T0, T1, r0, i0);
+    wg_tridiag(S, X.P, n);
+    double pivmin, span;
+    wg_bisect(S, n, pivmin, span);
+    int close = 0;
+    for (int j = threadIdx.x; j < n - 1; j += kWgThreads)
+        if (S.lam[j + 1] - S.lam[j] < 1e-3 * span) close = 1;
+    if (threadIdx.x == 0) S.flag = 0;
+    __syncthreads();
+    if (close) S.flag = 1;
+    __syncthreads();
+    bool ok = true;
+    if (S.flag == 0 && max_iter > 1) {
+        wg_twisted(S, X, n, pivmin);
+        for (int j = threadIdx.x; j < n; j += kWgThreads)
+            if (!isfinite(S.E[j])) ok = false;
+    } else {
+        ok = wg_ql(S, X.U, n, max_iter);
+    }
+    wg_backtransform(S, X.P, X.U, n);
+    const double2* U = X.U;
+    double2* W = X.W;
+    double2* VX = X.VX;
+    double2* VY = X.VY;
+    wg_gemm(S, W, n, [=](int i, int k) { return VX[i * n + k]; },
+            [=](int k, int j) { return U[k * n + j]; });
+    wg_gemm(S, VX, n, [=](int i, int k) { return c_conj(U[k * n + i]); },
+            [=](int k, int j) { return W[k * n + j]; });
+    wg_gemm(S, W, n, [=](int i, int k) { return VY[i * n + k]; },
+            [=](int k, int j) { return U[k * n + j]; });
+    wg_gemm(S, VY, n, [=](int i, int k) { return c_conj(U[k * n + i]); },
+            [=](int k, int j) { return W[k * n + j]; });
+    return ok;
+}
+
+// ---------------------------------------------------------------------------
+// k_forward_wg
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kWgThreads) void k_forward_wg(WgLaunch a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    WgLds& S = *reinterpret_cast<WgLds*>(smem_raw);
+    const double eta2 = a.eta * a.eta;
+    const WgScratch X = wg_scratch(reinterpret_cast<double2*>(a.scratch), a.slot_elems, blockIdx.x);
+    const double2* tbuf = reinterpret_cast<const double2*>(a.tbuf);
+    for (int item = blockIdx.x; item < a.item_count; item += gridDim.x) {
+        const BlockItem it = a.tb.blocks[a.item_begin + item];
+        const ModelDev md = a.tb.models[it.model];
+        const int n = md.n;
+        const long long nn = (long long)n * n;
+        const double2* T0 = tbuf + it.tbuf_off;
+        const double2* T1 = T0 + (long long)md.nR0 * nn;
+        const int* r0 = a.tb.r0val + md.r0_first;
+        const double* ef = a.e_fermi + md.f_off;
+        double* part = a.partial + (long long)it.slot * a.nF;
+        for (int kk = 0; kk < it.count; ++kk) {
+            const bool ok = wg_eigen_velocities(S, X, md, T0, T1, r0, it.i0 + kk, a.max_iter);
+            if (!ok) atomicOr(a.status, kStatNoConv);
+            for (int i = threadIdx.x; i < n; i += kWgThreads) {
+                double om = 0.0;
+                const double ei = S.E[i];
+                for (int m = 0; m < n; ++m) {
+                    if (m == i) continue;
+                    const double de = ei - S.E[m];
+                    const double den = de * de + eta2;
+                    if (den == 0.0) continue;
+                    const double2 x = X.VX[i * n + m], y = X.VY[m * n + i];
+                    om += (x.x * y.y + x.y * y.x) / den;
+                }
+                S.Om[i] = -2.0 * om;
+            }
+            __syncthreads();
+            for (int j = threadIdx.x; j < a.nF; j += kWgThreads) {
+                const double efj = ef[j];
+                double s = 0.0;
+                for (int b = 0; b < n; ++b) s += occupation(S.E[b], efj, a.kT) * S.Om[b];
+                if (!isfinite(s)) atomicOr(a.status, kStatNonFinite);
+                part[j] = (kk == 0) ? s : part[j] + s;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// phi(x) = sum_j sbar_j f_j(x) and its derivative
+__device__ __forceinline__ void wg_phi_at(double x, const double* __restrict__ ef,
+                                          const double* __restrict__ sb, int nF, double kT,
+                                          double& phi, double& dphi) {
+    double p = 0.0, d = 0.0;
+    for (int j = 0; j < nF; ++j) {
+        p += sb[j] * occupation(x, ef[j], kT);
+        if (kT > 0.0) {
+            const double ch = cosh(0.5 * (x - ef[j]) / kT);
+            d -= sb[j] / (4.0 * kT * ch * ch);
+        }
+    }
+    phi = p;
+    dphi = d;
+}
+
+// ---------------------------------------------------------------------------
+// k_adjoint_wg: reverse mode per k-point (see the one-wavefront notes in
+// kubo_device.hip for the formulas); writes the block's pencil partials.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kWgThreads) void k_adjoint_wg(WgLaunch a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    WgLds& S = *reinterpret_cast<WgLds*>(smem_raw);
+    const double eta2 = a.eta * a.eta;
+    const double scl = (a.kT > 0.0) ? fmin(a.eta, a.kT) : a.eta;
+    const double delta = 1e-5 * scl;
+    const WgScratch X = wg_scratch(reinterpret_cast<double2*>(a.scratch), a.slot_elems, blockIdx.x);
+    const double2* tbuf = reinterpret_cast<const double2*>(a.tbuf);
+    double2* pbuf = reinterpret_cast<double2*>(a.pbuf);
+    for (int item = blockIdx.x; item < a.item_count; item += gridDim.x) {
+        const BlockItem it = a.tb.blocks[a.item_begin + item];
+        const ModelDev md = a.tb.models[it.model];
+        const int n = md.n;
+        const long long nn = (long long)n * n;
+        const double2* T0 = tbuf + it.tbuf_off;
+        const double2* T1 = T0 + (long long)md.nR0 * nn;
+        double2* PH = pbuf + it.pbuf_off;
+        double2* PY = PH + (long long)md.nR0 * nn;
+        const int* r0 = a.tb.r0val + md.r0_first;
+        const double* ef = a.e_fermi + md.f_off;
+        const double* sb = a.sbar + md.f_off;
+        const double invN = 1.0 / (double)md.Nk;
+        for (int kk = 0; kk < it.count; ++kk) {
+            const bool ok = wg_eigen_velocities(S, X, md, T0, T1, r0, it.i0 + kk, a.max_iter);
+            if (!ok) atomicOr(a.status, kStatNoConv);
+            const double2* A = X.VX;
+            const double2* B = X.VY;
+            for (int b = threadIdx.x; b < n; b += kWgThreads) {
+                double p, d;
+                wg_phi_at(S.E[b], ef, sb, a.nF, a.kT, p, d);
+                S.phi[b] = p;
+                S.dphi[b] = d;
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < n * n; e += kWgThreads) {
+                const int m = e / n, q = e - (e / n) * n;
+                double k = 0.0;
+                if (m != q) {
+                    const double de = S.E[m] - S.E[q];
+                    k = (S.phi[m] - S.phi[q]) / (de * de + eta2);
+                }
+                X.K[e] = k;
+            }
+            __syncthreads();
+            // Hbar' (into W)
+            for (int e = threadIdx.x; e < n * n; e += kWgThreads) {
+                const int m = e / n, q = e - (e / n) * n;
+                const double de = S.E[m] - S.E[q];
+                double2 acc = c_make(0.0, 0.0);
+                if (m != q && fabs(de) >= delta) {
+                    for (int p = 0; p < n; ++p) {
+                        const double w = X.K[m * n + p] - X.K[q * n + p];
+                        double2 z = c_mul(B[m * n + p], A[p * n + q]);
+                        z = c_sub(z, c_mul(A[m * n + p], B[p * n + q]));
+                        acc = c_add(acc, c_scale(w, z));
+                    }
+                    acc = c_scale(invN / de, c_i(acc));
+                } else {
+                    const double xm = 0.5 * (S.E[m] + S.E[q]);
+                    double phx, dphx;
+                    if (m == q) {
+                        phx = S.phi[m];
+                        dphx = S.dphi[m];
+                    } else {
+                        wg_phi_at(xm, ef, sb, a.nF, a.kT, phx, dphx);
+                    }
+                    for (int p = 0; p < n; ++p) {
+                        const double x = xm - S.E[p];
+                        const double den = x * x + eta2;
+                        const double w = dphx / den - (phx - S.phi[p]) * 2.0 * x / (den * den);
+                        double2 z = c_mul(B[m * n + p], A[p * n + q]);
+                        z = c_sub(z, c_mul(A[m * n + p], B[p * n + q]));
+                        acc = c_add(acc, c_scale(w, z));
+                    }
+                    acc = c_scale(invN, c_i(acc));
+                }
+                X.W[e] = acc;
+            }
+            __syncthreads();
+            const double2* U = X.U;
+            double2* P = X.P;
+            double2* W = X.W;
+            double2* VX = X.VX;
+            double2* VY = X.VY;
+            const double* K = X.K;
+            // Hbar = U Hbar' U^+  (P = Hbar' U^+, W = U P)
+            wg_gemm(S, P, n, [=](int i, int k) { return W[i * n + k]; },
+                    [=](int k, int j) { return c_conj(U[j * n + k]); });
+            wg_gemm(S, W, n, [=](int i, int k) { return U[i * n + k]; },
+                    [=](int k, int j) { return P[k * n + j]; });
+            // vbar_x = U Abar U^+, Abar = (i/N) K o B   (P = Abar U^+, VY = U P)
+            wg_gemm(S, P, n, [=](int i, int k) { return c_scale(invN * K[i * n + k], c_i(VY[i * n + k])); },
+                    [=](int k, int j) { return c_conj(U[j * n + k]); });
+            wg_gemm(S, VY, n, [=](int i, int k) { return U[i * n + k]; },
+                    [=](int k, int j) { return P[k * n + j]; });
+            // vbar_y = U Bbar U^+, Bbar = -(i/N) K o A  (P = Bbar U^+, VX = U P)
+            wg_gemm(S, P, n, [=](int i, int k) { return c_scale(-invN * K[i * n + k], c_i(VX[i * n + k])); },
+                    [=](int k, int j) { return c_conj(U[j * n + k]); });
+            wg_gemm(S, VX, n, [=](int i, int k) { return U[i * n + k]; },
+                    [=](int k, int j) { return P[k * n + j]; });
+            for (long long e = threadIdx.x; e < (long long)md.nR0 * nn; e += kWgThreads) {
+                const int rho = (int)(e / nn);
+                const long long ij = e - (long long)rho * nn;
+                const double2 pc = c_conj(S.ph[rho]);
+                const double2 w = c_sub(W[ij], c_scale((double)r0[rho], c_i(VY[ij])));
+                const double2 h1 = c_mul(pc, w);
+                const double2 y1 = c_mul(pc, VX[ij]);
+                if (!isfinite(h1.x + h1.y + y1.x + y1.y)) atomicOr(a.status, kStatNonFinite);
+                if (kk == 0) {
+                    PH[e] = h1;
+                    PY[e] = y1;
+                } else {
+                    PH[e] = c_add(PH[e], h1);
+                    PY[e] = c_add(PY[e], y1);
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+static bool g_wg_attr = false;
+static hipError_t wg_attrs() {
+    if (g_wg_attr) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_forward_wg),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(WgLds));
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_adjoint_wg),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(WgLds));
+    if (e != hipSuccess) return e;
+    g_wg_attr = true;
+    return hipSuccess;
+}
+
+long long wg_slot_elems(int nmax) { return 7LL * nmax * nmax; }
+
+hipError_t launch_forward_wg(const WgLaunch& L, hipStream_t s) {
+    if (L.item_count <= 0) return hipSuccess;
+    hipError_t e = wg_attrs();
+    if (e != hipSuccess) return e;
+    const int grid = L.item_count < L.max_groups ? L.item_count : L.max_groups;
+    hipLaunchKernelGGL(k_forward_wg, dim3(grid), dim3(kWgThreads), sizeof(WgLds), s, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_wg(const WgLaunch& L, hipStream_t s) {
+    if (L.item_count <= 0) return hipSuccess;
+    hipError_t e = wg_attrs();
+    if (e != hipSuccess) return e;
+    const int grid = L.item_count < L.max_groups ? L.item_count : L.max_groups;
+    hipLaunchKernelGGL(k_adjoint_wg, dim3(grid), dim3(kWgThreads), sizeof(WgLds), s, L);
+    return hipGetLastError();
+}
+
+}  // namespace kubo

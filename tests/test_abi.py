@@ -91,6 +91,8 @@ def test_plan_rejects_bad_tile():
     t = kubo.kubo_tile()
     t.n_orb, t.threads, t.k_block, t.reserved = 4, 96, 8, 0
     assert _plan_status([d], tiles=[t])[0] == kubo.KUBO_E_INVALID
+    t.n_orb, t.threads = 40, 64
+    assert _plan_status([d], tiles=[t])[0] == kubo.KUBO_E_INVALID
 
 
 def test_plan_unsupported_size():

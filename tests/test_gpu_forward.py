@@ -69,6 +69,41 @@ def test_small_models_parity(torch, oracle, n, L, grid, kT):
     assert_sigma_parity(got[0], ref, sabs, what=f"n={n}")
 
 
+@pytest.mark.parametrize("n,L,grid,kT", [(33, 1, (3, 2, 2), 0.02), (40, 1, (2, 3, 2), 0.0),
+                                         (64, 1, (2, 2, 3), 0.01), (97, 1, (2, 2, 1), 0.02),
+                                         (128, 1, (2, 1, 2), 0.01)])
+def test_large_models_parity(torch, oracle, n, L, grid, kT):
+    """The workgroup-per-k-point path (n > 32) against the oracle."""
+    m = synth.random_model(n, L, 1.0, 600 + n)
+    lo, hi = oracle.band_range(m.t, m.R, (2, 2, 2))
+    ef = np.linspace(lo - 0.5, hi + 0.5, 6)
+    print(f"case large n={n} grid={grid}", flush=True)
+    got, _ = run_gpu(torch, [m], grid, ef, 1e-3, kT)
+    ref, sabs = oracle.ahc(m.t, m.R, grid, ef, 1e-3, kT, with_sabs=True)
+    assert_sigma_parity(got[0], ref, sabs, what=f"n={n}")
+
+
+@pytest.mark.parametrize("n,grid", [(5, (4, 3, 2)), (16, (3, 3, 2)), (32, (3, 2, 2))])
+def test_workgroup_kernel_for_small_n(torch, oracle, n, grid):
+    """Small n routed to the workgroup-per-k-point kernel (tile threads = 256)."""
+    m = synth.random_model(n, 1, 1.0, 620 + n)
+    lo, hi = oracle.band_range(m.t, m.R, (2, 2, 2))
+    ef = np.linspace(lo, hi, 5)
+    got, _ = run_gpu(torch, [m], grid, ef, 1e-3, 0.01, tiles=[(n, 256, 3)])
+    ref, sabs = oracle.ahc(m.t, m.R, grid, ef, 1e-3, 0.01, with_sabs=True)
+    assert_sigma_parity(got[0], ref, sabs, what=f"wg n={n}")
+
+
+@pytest.mark.parametrize("n", [6, 24])
+def test_degenerate_spectrum_parity(torch, oracle, n):
+    """t (x) I_2: every eigenvalue doubly degenerate (the clustered-spectrum path)."""
+    m = synth.doubled(synth.random_model(n, 1, 1.0, 640 + n))
+    ef = np.array([-1.0, 0.0, 1.3])
+    got, _ = run_gpu(torch, [m], (3, 2, 2), ef, 1e-2, 0.02)
+    ref, sabs = oracle.ahc(m.t, m.R, (3, 2, 2), ef, 1e-2, 0.02, with_sabs=True)
+    assert_sigma_parity(got[0], ref, sabs, what=f"doubled n={2 * n}")
+
+
 @pytest.mark.parametrize("u", [-1.0, 1.0, 3.0])
 def test_qwz_quantised_on_gpu(torch, u):
     m = synth.qwz_model(u)
@@ -98,7 +133,7 @@ def test_slabs_add_up_and_determinism(torch):
 
 
 def test_multi_model_plan_equals_single_plans(torch):
-    ms = [synth.random_model(n, 1, 1.0, 900 + n) for n in (3, 8, 17, 30)]
+    ms = [synth.random_model(n, 1, 1.0, 900 + n) for n in (3, 8, 17, 30, 44)]
     ef = np.linspace(-2, 2, 4)
     grid = (6, 4, 3)
     both, _ = run_gpu(torch, ms, grid, ef, 1e-3, 0.02)
