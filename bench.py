@@ -49,6 +49,80 @@ def fermi_levels(cfg: int, wl):
     return np.array([synth.fermi_levels(lo, hi, wl.n_fermi) for lo, hi in ranges])
 
 
+def measure_batched(steps: int, warmup: int):
+    """The 200-model workload: one batched plan replayed as a hipGraph vs one plan per model."""
+    import torch
+
+    from paper_2309_06675_amd import kubo, synth
+
+    wl = synth.workload(2)
+    ef = fermi_levels(2, wl)
+    dev = "cuda:0"
+    s = torch.cuda.Stream(dev)
+    t_all = kubo.to_device_t(wl.models, dev)
+    efd = torch.from_numpy(ef).to(dev)
+    total_k = len(wl.models) * wl.n_k
+    flops = sum(nominal_flops_per_k(m.n, m.n_R, wl.n_fermi, wl.kT > 0) for m in wl.models) * wl.n_k
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    out = {}
+    with torch.cuda.stream(s):
+        os.environ["KUBO_CHUNK_MB"] = "4096"
+        plan = kubo.Plan(wl.models, grid=wl.grid, n_fermi=wl.n_fermi,
+                         flags=kubo.KUBO_F_GRAPH | kubo.KUBO_F_FORWARD_ONLY, device=dev)
+        sig = torch.empty(len(wl.models), wl.n_fermi, dtype=torch.float64, device=dev)
+        for _ in range(warmup):
+            plan.forward(t_all, efd, wl.eta, wl.kT, out=sig)
+        torch.cuda.synchronize()
+        start.record(s)
+        for _ in range(steps):
+            plan.forward(t_all, efd, wl.eta, wl.kT, out=sig)
+        stop.record(s)
+        torch.cuda.synchronize()
+        ms_b = start.elapsed_time(stop) / steps
+        st = plan.device_status()
+        if st != kubo.KUBO_OK:
+            raise SystemExit(f"batched device status: {kubo.kubo_status_string(st)}")
+        sig_b = sig.cpu().numpy()
+        del plan
+        # plain path: one plan (and workspace) per model, launched one after another
+        plans, ts, sigs = [], [], []
+        off = 0
+        os.environ["KUBO_CHUNK_MB"] = "256"
+        for i, m in enumerate(wl.models):
+            plans.append(kubo.Plan([m], grid=wl.grid, n_fermi=wl.n_fermi,
+                                   flags=kubo.KUBO_F_FORWARD_ONLY, device=dev))
+            cnt = m.t.size
+            ts.append(t_all[off:off + cnt])
+            off += cnt
+            sigs.append(torch.empty(1, wl.n_fermi, dtype=torch.float64, device=dev))
+        for _ in range(warmup):
+            for i, p in enumerate(plans):
+                p.forward(ts[i], efd[i:i + 1], wl.eta, wl.kT, out=sigs[i])
+        torch.cuda.synchronize()
+        start.record(s)
+        for _ in range(steps):
+            for i, p in enumerate(plans):
+                p.forward(ts[i], efd[i:i + 1], wl.eta, wl.kT, out=sigs[i])
+        stop.record(s)
+        torch.cuda.synchronize()
+        ms_p = start.elapsed_time(stop) / steps
+        sig_p = torch.cat(sigs).cpu().numpy()
+        os.environ.pop("KUBO_CHUNK_MB", None)
+    out["workload"] = wl.name
+    out["models"] = len(wl.models)
+    out["k_points_per_step"] = total_k
+    out["batched_graph"] = {"ms_per_step": ms_b, "k_points_per_s": total_k / (ms_b / 1e3),
+                            "tflops_nominal": flops / (ms_b / 1e3) / 1e12,
+                            "frac": flops / (ms_b / 1e3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS}
+    out["plain_per_model"] = {"ms_per_step": ms_p, "k_points_per_s": total_k / (ms_p / 1e3),
+                              "tflops_nominal": flops / (ms_p / 1e3) / 1e12,
+                              "frac": flops / (ms_p / 1e3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS}
+    out["batched_over_plain"] = ms_p / ms_b
+    out["max_abs_diff_batched_vs_plain"] = float(np.abs(sig_b - sig_p).max())
+    return out
+
+
 def cpu_baseline(model, wl, ef, sample: int):
     """The CPU oracle, untuned, on a contiguous slab of `sample` k-points."""
     from oracle import oracle as O
@@ -76,6 +150,8 @@ def main(argv=None):
                     help="per-k kernel: 64 = one wavefront, 256 = one workgroup (0 = default)")
     ap.add_argument("--adjoint-steps", type=int, default=1,
                     help="timed backward passes for the adjoint/forward ratio (0 skips)")
+    ap.add_argument("--batched-steps", type=int, default=1,
+                    help="timed steps of the 200-model batched workload (0 skips)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -93,7 +169,7 @@ def main(argv=None):
     ef = fermi_levels(cfg, wl)
     dev = "cuda:0"
     torch.cuda.set_device(0)
-    tiles = None
+    tiles = "auto"
     if args.k_block > 0 or args.threads > 0:
         tiles = [(model.n, args.threads, args.k_block if args.k_block > 0 else 32)]
     plan = kubo.Plan([model], grid=wl.grid, n_fermi=wl.n_fermi, flags=kubo.KUBO_F_TIMING,
@@ -172,6 +248,8 @@ def main(argv=None):
                           "adjoint_forward_ratio": bms / (ms / args.steps),
                           "kernel_ms_per_step": plan.kernel_time(1)[0] / args.adjoint_steps,
                           "grad_checksum": float(grad.abs().sum().item())}
+    if args.batched_steps > 0:
+        out["batched"] = measure_batched(args.batched_steps, 1)
     if args.cpu_sample > 0:
         out["cpu_baseline"] = cpu_baseline(model, wl, ef[0], args.cpu_sample)
     print(json.dumps(out), flush=True)

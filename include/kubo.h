@@ -85,6 +85,8 @@ typedef struct {
                                     while the pointers and scalars stay the same */
 #define KUBO_F_TIMING 0x2u       /* record HIP events around every launch of the per-k
                                     kernels (ignored while KUBO_F_GRAPH replays) */
+#define KUBO_F_FORWARD_ONLY 0x4u /* size the workspace for kubo_ahc only; kubo_ahc_backward
+                                    then returns KUBO_E_INVALID */
 #define KUBO_F_DEBUG_SWEEPCAP 0x100u /* cap the iterative eigensolver at one iteration (one
                                     sweep) and route every k-point through it, so that the
                                     device status reports KUBO_E_NOCONV (tests of that path) */
@@ -98,7 +100,11 @@ typedef struct {
  *   n_fermi         Fermi levels per model, 1 <= n_fermi <= 4096
  *   flags           KUBO_F_* bits; unknown bits are KUBO_E_INVALID
  *   tiles, n_tiles  optional launch shapes (NULL/0 = built-in defaults)
- *   workspace_bytes out: device workspace the plan needs (forward and backward)
+ *   workspace_bytes out: device workspace the plan needs (forward and backward,
+ *                   or forward only with KUBO_F_FORWARD_ONLY)
+ * The k-grid is processed in chunks of kx pencils whose partial Bloch sums fit
+ * a buffer of KUBO_CHUNK_MB megabytes (environment variable read here; default
+ * 512): larger chunks mean fewer launches and a larger workspace.
  * Errors: KUBO_E_INVALID for NULL pointers, n_orb < 1, n_R < 1, grid < 1,
  * duplicate R, an R whose negative is missing, a slab outside the grid or a
  * bad tile; KUBO_E_UNSUPPORTED for n_orb > 128.

@@ -319,7 +319,7 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
     P->off_tbuf = off;
     off = align_up(off + max_t);
     P->off_pbuf = off;
-    off = align_up(off + max_p);
+    if (!(P->flags & KUBO_F_FORWARD_ONLY)) off = align_up(off + max_p);
     P->off_partial = off;
     off = align_up(off + (size_t)P->n_slots * nF * 8);
     {
@@ -344,7 +344,8 @@ kubo_status validate(const kubo_model_desc* models, int n_models, int nF, uint32
                      const kubo_tile* tiles, int n_tiles) {
     if (!models || n_models < 1) return KUBO_E_INVALID;
     if (nF < 1 || nF > kMaxFermi) return KUBO_E_INVALID;
-    if (flags & ~(KUBO_F_GRAPH | KUBO_F_TIMING | KUBO_F_DEBUG_SWEEPCAP)) return KUBO_E_INVALID;
+    if (flags & ~(KUBO_F_GRAPH | KUBO_F_TIMING | KUBO_F_FORWARD_ONLY | KUBO_F_DEBUG_SWEEPCAP))
+        return KUBO_E_INVALID;
     if (n_tiles < 0 || (n_tiles > 0 && !tiles)) return KUBO_E_INVALID;
     for (int i = 0; i < n_tiles; ++i) {
         const kubo_tile& t = tiles[i];
@@ -623,6 +624,7 @@ kubo_status kubo_ahc_backward(kubo_plan_t plan, const double* t, const double* e
                               double eta, double kT, const double* sigma_bar, double* grad_t,
                               void* workspace, size_t workspace_bytes, void* stream) {
     if (!plan || !t || !e_fermi || !sigma_bar || !grad_t) return KUBO_E_INVALID;
+    if (plan->flags & KUBO_F_FORWARD_ONLY) return KUBO_E_INVALID;
     if (!finite_nonneg(eta) || !finite_nonneg(kT) || !(eta > 0.0)) return KUBO_E_INVALID;
     if (!workspace || workspace_bytes < plan->total) return KUBO_E_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);

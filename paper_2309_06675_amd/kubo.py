@@ -34,6 +34,7 @@ KUBO_E_NONFINITE = 6
 
 KUBO_F_GRAPH = 0x1
 KUBO_F_TIMING = 0x2
+KUBO_F_FORWARD_ONLY = 0x4
 KUBO_F_DEBUG_SWEEPCAP = 0x100
 
 EXPORTED = ("kubo_plan", "kubo_ahc", "kubo_ahc_backward", "kubo_plan_device_status",
@@ -181,11 +182,15 @@ class Plan:
     """A kubo plan for one or more models, with its own device workspace."""
 
     def __init__(self, models: Iterable, grid=None, n_fermi: int = 1, flags: int = 0,
-                 tiles: Optional[Sequence[tuple]] = None, slabs: Optional[Sequence[tuple]] = None,
-                 device: str = "cuda"):
+                 tiles="auto", slabs: Optional[Sequence[tuple]] = None, device: str = "cuda"):
         """models: objects with .n and .R (e.g. synth.TBModel); grid: one grid or one per model;
-        slabs: optional (k_begin, k_count) per model; tiles: (n_orb, threads, k_block) tuples."""
+        slabs: optional (k_begin, k_count) per model; tiles: (n_orb, threads, k_block) tuples,
+        None for the built-in defaults, or "auto" for the autotuner's cache (if any)."""
         models = list(models)
+        if isinstance(tiles, str) and tiles == "auto":
+            from . import autotune
+
+            tiles = autotune.lookup([m.n for m in models]) or None
         grids = [grid] * len(models) if (grid is None or np.ndim(grid[0]) == 0) else list(grid)
         keep = []
         descs = []
