@@ -123,6 +123,44 @@ def measure_batched(steps: int, warmup: int):
     return out
 
 
+def kernel_source_digest() -> str:
+    """sha256 of the sources of the dominant kernel (the one-wavefront per-k kernel)."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("kubo_wave.hip", "kubo_cplx.h", "kubo_internal.h", "kubo_launch.h"):
+        with open(os.path.join(ROOT, "paper_2309_06675_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter runs
+    (profiles/traffic_k_forward_wave_n32.json), or None if the kernel changed since."""
+    path = os.path.join(ROOT, "profiles", "traffic_k_forward_wave_n32.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_sha256") != kernel_source_digest():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def copy_calibration(mbytes: int):
+    """One device-to-device copy of a known size (to scale the FETCH/WRITE counters)."""
+    import torch
+
+    n = mbytes * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n * 8, "read_bytes": n * 8, "write_bytes": n * 8}), flush=True)
+    return 0
+
+
 def cpu_baseline(model, wl, ef, sample: int):
     """The CPU oracle, untuned, on a contiguous slab of `sample` k-points."""
     from oracle import oracle as O
@@ -152,7 +190,11 @@ def main(argv=None):
                     help="timed backward passes for the adjoint/forward ratio (0 skips)")
     ap.add_argument("--batched-steps", type=int, default=1,
                     help="timed steps of the 200-model batched workload (0 skips)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
+                    help="only run one device copy of MB megabytes (counter calibration)")
     args = ap.parse_args(argv)
+    if args.copy_calibration > 0:
+        return copy_calibration(args.copy_calibration)
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(k-slabs shard across GPUs by design, but this build runs on one GPU only)",
@@ -182,9 +224,10 @@ def main(argv=None):
     for _ in range(args.warmup):
         plan.forward(t, efd, wl.eta, wl.kT, out=sigma)
     torch.cuda.synchronize()
-    st = plan.device_status()
-    if st != kubo.KUBO_OK:
-        raise SystemExit(f"device status after warm-up: {kubo.kubo_status_string(st)}")
+    if args.warmup > 0:
+        st = plan.device_status()
+        if st != kubo.KUBO_OK:
+            raise SystemExit(f"device status after warm-up: {kubo.kubo_status_string(st)}")
     plan.kernel_time(0, reset=True)
 
     start = torch.cuda.Event(enable_timing=True)
@@ -223,7 +266,7 @@ def main(argv=None):
                    "eta": wl.eta, "kT": wl.kT, "model_seed": 1000, "parallelism": "single-gpu"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-                     "traffic": None, "kernel": "k_forward (per-k fused kernel)",
+                     "traffic": recorded_traffic(), "kernel": "k_forward_wave<32> (per-k fused)",
                      "flops_per_k": fpk, "kernel_ms_per_step": k_ms / args.steps,
                      "launches_per_step": launches / args.steps},
         "sigma_checksum": float(sigma.sum().item()),

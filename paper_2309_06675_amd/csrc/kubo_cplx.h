@@ -73,4 +73,19 @@ __device__ __forceinline__ double2 c_mulc(double2 a, double2 b) {
     return c_make(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
 }
 
+// Work-item schedule of the persistent per-k kernels.  Workgroups are handed to
+// the eight XCDs round-robin (workgroup b runs on XCD b % 8), so each XCD gets a
+// contiguous share of the item list: the k-blocks of one pencil, which read the
+// same partial Bloch sums, then run inside one XCD and share its L2.
+struct ItemSchedule {
+    int next, end, step;
+};
+__device__ __forceinline__ ItemSchedule xcd_schedule(int count) {
+    const int G = (int)gridDim.x;
+    if (G < 8 || (G & 7) != 0) return ItemSchedule{(int)blockIdx.x, count, G};
+    const int x = (int)blockIdx.x & 7, j = (int)blockIdx.x >> 3;
+    const int b = (int)((long long)count * x / 8), e = (int)((long long)count * (x + 1) / 8);
+    return ItemSchedule{b + j, e, G >> 3};
+}
+
 }  // namespace kubo

@@ -84,12 +84,18 @@ struct kubo_plan_s {
     long long total_k = 0;
     std::vector<ModelDev> models;
     std::vector<int> r0val, grp_start, grp_r, grp_R1, grp_R2, grp_rho, negr;
-    std::vector<GaccRange> granges;
     int max_nR = 0;
     long long max_nn = 0;
-    std::vector<PencilItem> pencils;
-    std::vector<BlockItem> blocks;
-    std::vector<Chunk> chunks;
+    // forward (partial Bloch sums only) and backward (plus pencil-sum buffers)
+    // chunkings of the same k-blocks
+    struct ChunkSet {
+        std::vector<PencilItem> pencils;
+        std::vector<BlockItem> blocks;
+        std::vector<GaccRange> granges;
+        std::vector<Chunk> chunks;
+        size_t max_t = 0, max_p = 0;
+        size_t tab_pencils = 0, tab_blocks = 0, tab_granges = 0;
+    } fwd, bwd;
     int n_slots = 0;
     long long t_elems = 0;  // complex elements of t (all models)
     // workspace layout
@@ -98,7 +104,7 @@ struct kubo_plan_s {
     long long slot_elems = 0;
     int wg_groups = 512;
     std::vector<unsigned char> blob;
-    size_t tab_off[11] = {0};
+    size_t tab_off[10] = {0};
     const void* uploaded_ws = nullptr;
     CachedGraph graph_fwd, graph_bwd;
     int max_groups = 2048;
@@ -115,8 +121,9 @@ struct kubo_plan_s {
 
 namespace {
 
-Tables device_tables(const kubo_plan_s* p, unsigned char* ws) {
+Tables device_tables(const kubo_plan_s* p, unsigned char* ws, bool backward) {
     unsigned char* b = ws + p->off_tables;
+    const kubo_plan_s::ChunkSet& cs = backward ? p->bwd : p->fwd;
     Tables t;
     t.models = reinterpret_cast<const ModelDev*>(b + p->tab_off[0]);
     t.r0val = reinterpret_cast<const int*>(b + p->tab_off[1]);
@@ -125,10 +132,10 @@ Tables device_tables(const kubo_plan_s* p, unsigned char* ws) {
     t.grp_R1 = reinterpret_cast<const int*>(b + p->tab_off[4]);
     t.grp_R2 = reinterpret_cast<const int*>(b + p->tab_off[5]);
     t.negr = reinterpret_cast<const int*>(b + p->tab_off[6]);
-    t.pencils = reinterpret_cast<const PencilItem*>(b + p->tab_off[7]);
-    t.blocks = reinterpret_cast<const BlockItem*>(b + p->tab_off[8]);
     t.grp_rho = reinterpret_cast<const int*>(b + p->tab_off[9]);
-    t.granges = reinterpret_cast<const GaccRange*>(b + p->tab_off[10]);
+    t.pencils = reinterpret_cast<const PencilItem*>(b + cs.tab_pencils);
+    t.blocks = reinterpret_cast<const BlockItem*>(b + cs.tab_blocks);
+    t.granges = reinterpret_cast<const GaccRange*>(b + cs.tab_granges);
     return t;
 }
 
@@ -246,57 +253,77 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
     P->t_elems = t_off;
     P->n_slots = slot;
 
-    // chunks: consecutive pencils while the T and P regions stay under the cap
-    size_t max_t = 0, max_p = 0;
-    Chunk cur;
-    std::vector<std::vector<BlockItem>> cls_blocks(kNumClasses);
-    auto flush = [&]() {
-        if (cur.pencil_count == 0) return;
-        cur.grange_begin = (int)P->granges.size();
-        for (int c = 0; c < kNumClasses; ++c) {
-            cur.cls[c].begin = (int)P->blocks.size();
-            cur.cls[c].count = (int)cls_blocks[c].size();
-            cur.cls_kpts[c] = 0;
-            for (auto& b : cls_blocks[c]) {
-                const int bi = (int)P->blocks.size();
-                if (P->granges.size() > (size_t)cur.grange_begin &&
-                    P->granges.back().model == b.model &&
-                    P->granges.back().begin + P->granges.back().count == bi)
-                    P->granges.back().count++;
-                else
-                    P->granges.push_back(GaccRange{b.model, bi, 1, 0});
-                P->blocks.push_back(b);
-                cur.cls_kpts[c] += b.count;
+    // chunks: consecutive pencils while the T (and, backward, P) regions stay under the cap
+    auto chunkify = [&](bool with_p, kubo_plan_s::ChunkSet& cs) {
+        Chunk cur;
+        std::vector<std::vector<BlockItem>> cls_blocks(kNumClasses);
+        auto flush = [&]() {
+            if (cur.pencil_count == 0) return;
+            cur.grange_begin = (int)cs.granges.size();
+            if (!with_p) {
+                // forward: deal whole pencils round-robin into eight bins, one per XCD
+                // share of the persistent grid, so every XCD sees the same mix of models
+                for (int c = 0; c < kNumClasses; ++c) {
+                    std::vector<BlockItem> bins[8];
+                    int p = -1;
+                    for (size_t i = 0; i < cls_blocks[c].size(); ++i) {
+                        const BlockItem& b = cls_blocks[c][i];
+                        if (i == 0 || b.tbuf_off != cls_blocks[c][i - 1].tbuf_off) ++p;
+                        bins[p & 7].push_back(b);
+                    }
+                    cls_blocks[c].clear();
+                    for (auto& bin : bins) cls_blocks[c].insert(cls_blocks[c].end(), bin.begin(), bin.end());
+                }
             }
-            cls_blocks[c].clear();
+            for (int c = 0; c < kNumClasses; ++c) {
+                cur.cls[c].begin = (int)cs.blocks.size();
+                cur.cls[c].count = (int)cls_blocks[c].size();
+                cur.cls_kpts[c] = 0;
+                for (auto& b : cls_blocks[c]) {
+                    const int bi = (int)cs.blocks.size();
+                    if (cs.granges.size() > (size_t)cur.grange_begin &&
+                        cs.granges.back().model == b.model &&
+                        cs.granges.back().begin + cs.granges.back().count == bi)
+                        cs.granges.back().count++;
+                    else
+                        cs.granges.push_back(GaccRange{b.model, bi, 1, 0});
+                    cs.blocks.push_back(b);
+                    cur.cls_kpts[c] += b.count;
+                }
+                cls_blocks[c].clear();
+            }
+            cur.grange_count = (int)cs.granges.size() - cur.grange_begin;
+            cs.max_t = std::max(cs.max_t, cur.tbytes);
+            cs.max_p = std::max(cs.max_p, cur.pbytes);
+            cs.chunks.push_back(cur);
+            cur = Chunk();
+            cur.pencil_begin = (int)cs.pencils.size();
+        };
+        cur.pencil_begin = 0;
+        for (const auto& pb0 : all) {
+            PB pb = pb0;
+            if (cur.pencil_count > 0 &&
+                (cur.tbytes + pb.tbytes > cap || (with_p && cur.pbytes + pb.pbytes > cap)))
+                flush();
+            PencilItem pi = pb.pi;
+            pi.tbuf_off = (long long)(cur.tbytes / 16);
+            long long poff = (long long)(cur.pbytes / 16);
+            const long long mat = (long long)(pb.tbytes / 16);
+            for (auto& b : pb.blocks) {
+                b.tbuf_off = pi.tbuf_off;
+                b.pbuf_off = poff;
+                poff += mat;
+                cls_blocks[pb.cls].push_back(b);
+            }
+            cs.pencils.push_back(pi);
+            cur.pencil_count++;
+            cur.tbytes += pb.tbytes;
+            cur.pbytes += pb.pbytes;
         }
-        cur.grange_count = (int)P->granges.size() - cur.grange_begin;
-        max_t = std::max(max_t, cur.tbytes);
-        max_p = std::max(max_p, cur.pbytes);
-        P->chunks.push_back(cur);
-        cur = Chunk();
-        cur.pencil_begin = (int)P->pencils.size();
+        flush();
     };
-    cur.pencil_begin = 0;
-    for (auto& pb : all) {
-        if (cur.pencil_count > 0 && (cur.tbytes + pb.tbytes > cap || cur.pbytes + pb.pbytes > cap))
-            flush();
-        PencilItem pi = pb.pi;
-        pi.tbuf_off = (long long)(cur.tbytes / 16);
-        long long poff = (long long)(cur.pbytes / 16);
-        const long long mat = (long long)(pb.tbytes / 16);
-        for (auto& b : pb.blocks) {
-            b.tbuf_off = pi.tbuf_off;
-            b.pbuf_off = poff;
-            poff += mat;
-            cls_blocks[pb.cls].push_back(b);
-        }
-        P->pencils.push_back(pi);
-        cur.pencil_count++;
-        cur.tbytes += pb.tbytes;
-        cur.pbytes += pb.pbytes;
-    }
-    flush();
+    chunkify(false, P->fwd);
+    if (!(flags & KUBO_F_FORWARD_ONLY)) chunkify(true, P->bwd);
 
     // index tables, uploaded into the workspace on first use
     append_blob(P->blob, P->tab_off[0], P->models);
@@ -306,10 +333,14 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
     append_blob(P->blob, P->tab_off[4], P->grp_R1);
     append_blob(P->blob, P->tab_off[5], P->grp_R2);
     append_blob(P->blob, P->tab_off[6], P->negr);
-    append_blob(P->blob, P->tab_off[7], P->pencils);
-    append_blob(P->blob, P->tab_off[8], P->blocks);
     append_blob(P->blob, P->tab_off[9], P->grp_rho);
-    append_blob(P->blob, P->tab_off[10], P->granges);
+    for (kubo_plan_s::ChunkSet* cs : {&P->fwd, &P->bwd}) {
+        append_blob(P->blob, cs->tab_pencils, cs->pencils);
+        append_blob(P->blob, cs->tab_blocks, cs->blocks);
+        append_blob(P->blob, cs->tab_granges, cs->granges);
+    }
+    const size_t max_t = std::max(P->fwd.max_t, P->bwd.max_t);
+    const size_t max_p = P->bwd.max_p;
 
     size_t off = kAlign;  // status word
     P->off_tables = off;
@@ -327,12 +358,11 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
         for (const auto& md : P->models) nmax = std::max(nmax, md.n);
         P->slot_elems = wg_slot_elems(nmax);
         int most = 1;
-        for (const Chunk& c : P->chunks) {
-            int cnt = 0;
-            for (int k = 0; k < kNumClasses; ++k) cnt = std::max(cnt, c.cls[k].count);
-            most = std::max(most, cnt);
-        }
+        for (const kubo_plan_s::ChunkSet* cs : {&P->fwd, &P->bwd})
+            for (const Chunk& c : cs->chunks)
+                for (int k = 0; k < kNumClasses; ++k) most = std::max(most, c.cls[k].count);
         P->wg_groups = std::min(P->wg_groups, most);
+        if (P->wg_groups >= 8) P->wg_groups &= ~7;  // whole XCD rounds
     }
     P->off_scratch = off;
     off = align_up(off + (size_t)P->wg_groups * (size_t)P->slot_elems * 16);
@@ -434,7 +464,7 @@ struct TimedScope {
 
 kubo_status enqueue_forward(kubo_plan_s* P, const double* t, const double* ef, double eta,
                             double kT, double* sigma, unsigned char* ws, hipStream_t s) {
-    const Tables tb = device_tables(P, ws);
+    const Tables tb = device_tables(P, ws, false);
     unsigned* status = reinterpret_cast<unsigned*>(ws);
     double* tp = reinterpret_cast<double*>(ws + P->off_tp);
     double* tbuf = reinterpret_cast<double*>(ws + P->off_tbuf);
@@ -443,7 +473,7 @@ kubo_status enqueue_forward(kubo_plan_s* P, const double* t, const double* ef, d
     const int max_iter = (P->flags & KUBO_F_DEBUG_SWEEPCAP) ? 1 : kMaxSweeps;
     HIP_TRY(launch_clear(status, s));
     HIP_TRY(launch_hermproj(tb, P->n_models, P->t_elems, t, tp, s));
-    for (const Chunk& c : P->chunks) {
+    for (const Chunk& c : P->fwd.chunks) {
         HIP_TRY(launch_pencil(tb, c.pencil_begin, c.pencil_count, tp, tbuf, s));
         for (int k = 0; k < kNumClasses; ++k) {
             if (c.cls[k].count == 0) continue;
@@ -494,7 +524,7 @@ kubo_status enqueue_forward(kubo_plan_s* P, const double* t, const double* ef, d
 kubo_status enqueue_backward(kubo_plan_s* P, const double* t, const double* ef, double eta,
                              double kT, const double* sbar, double* grad, unsigned char* ws,
                              hipStream_t s) {
-    const Tables tb = device_tables(P, ws);
+    const Tables tb = device_tables(P, ws, true);
     unsigned* status = reinterpret_cast<unsigned*>(ws);
     double* tp = reinterpret_cast<double*>(ws + P->off_tp);
     double* tbuf = reinterpret_cast<double*>(ws + P->off_tbuf);
@@ -504,7 +534,7 @@ kubo_status enqueue_backward(kubo_plan_s* P, const double* t, const double* ef, 
     HIP_TRY(launch_clear(status, s));
     HIP_TRY(launch_hermproj(tb, P->n_models, P->t_elems, t, tp, s));
     HIP_TRY(launch_zero(grad, 2 * P->t_elems, s));
-    for (const Chunk& c : P->chunks) {
+    for (const Chunk& c : P->bwd.chunks) {
         HIP_TRY(launch_pencil(tb, c.pencil_begin, c.pencil_count, tp, tbuf, s));
         for (int k = 0; k < kNumClasses; ++k) {
             if (c.cls[k].count == 0) continue;

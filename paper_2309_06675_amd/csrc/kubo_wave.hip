@@ -501,7 +501,8 @@ __global__ __launch_bounds__(64) void k_forward_wave(FwdLaunch a) {
     const double eta2 = a.eta * a.eta;
     const int max_iter = a.max_sweeps >= kMaxSweeps ? 30 : 1;
     const double2* tbuf = reinterpret_cast<const double2*>(a.tbuf);
-    for (int item = blockIdx.x; item < a.item_count; item += gridDim.x) {
+    for (ItemSchedule sc = xcd_schedule(a.item_count); sc.next < sc.end; sc.next += sc.step) {
+        const int item = sc.next;
         const BlockItem it = a.tb.blocks[a.item_begin + item];
         const ModelDev md = a.tb.models[it.model];
         const int n = md.n;

@@ -519,7 +519,8 @@ __global__ __launch_bounds__(kWgThreads) void k_forward_wg(WgLaunch a) {
     const double eta2 = a.eta * a.eta;
     const WgScratch X = wg_scratch(reinterpret_cast<double2*>(a.scratch), a.slot_elems, blockIdx.x);
     const double2* tbuf = reinterpret_cast<const double2*>(a.tbuf);
-    for (int item = blockIdx.x; item < a.item_count; item += gridDim.x) {
+    for (ItemSchedule sc = xcd_schedule(a.item_count); sc.next < sc.end; sc.next += sc.step) {
+        const int item = sc.next;
         const BlockItem it = a.tb.blocks[a.item_begin + item];
         const ModelDev md = a.tb.models[it.model];
         const int n = md.n;
@@ -587,7 +588,8 @@ __global__ __launch_bounds__(kWgThreads) void k_adjoint_wg(WgLaunch a) {
     const WgScratch X = wg_scratch(reinterpret_cast<double2*>(a.scratch), a.slot_elems, blockIdx.x);
     const double2* tbuf = reinterpret_cast<const double2*>(a.tbuf);
     double2* pbuf = reinterpret_cast<double2*>(a.pbuf);
-    for (int item = blockIdx.x; item < a.item_count; item += gridDim.x) {
+    for (ItemSchedule sc = xcd_schedule(a.item_count); sc.next < sc.end; sc.next += sc.step) {
+        const int item = sc.next;
         const BlockItem it = a.tb.blocks[a.item_begin + item];
         const ModelDev md = a.tb.models[it.model];
         const int n = md.n;
