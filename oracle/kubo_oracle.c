@@ -50,7 +50,8 @@
 typedef double complex cplx;
 
 #define ORACLE_MAX_SWEEPS 60
-#define ORACLE_KCHUNK 64 /* k-points per fixed summation chunk */
+#define ORACLE_KCHUNK 4        /* k-points per fixed summation chunk of sigma */
+#define ORACLE_GRAD_KCHUNK 64  /* k-points per gradient chunk (one G copy each) */
 
 /* ------------------------------------------------------------------ */
 /* Occupations (Eq. (3) uses a step; kT > 0 generalises to Fermi-Dirac) */
@@ -557,7 +558,7 @@ int oracle_ahc_grad(int n, int nR, const int* R, const double* t, const int* gri
     long Nk = (long)grid[0] * grid[1] * grid[2];
     size_t nn = (size_t)n * n;
     size_t gsz = (size_t)nR * nn;
-    long nchunk = (k_count + ORACLE_KCHUNK - 1) / ORACLE_KCHUNK;
+    long nchunk = (k_count + ORACLE_GRAD_KCHUNK - 1) / ORACLE_GRAD_KCHUNK;
     cplx* Gc = calloc((size_t)nchunk * gsz, sizeof(cplx));
     weights W = {nF, EF, sbar, kT, eta};
     int bad = 0;
@@ -581,8 +582,8 @@ int oracle_ahc_grad(int n, int nR, const int* R, const double* t, const int* gri
 #pragma omp for schedule(dynamic, 1)
         for (long c = 0; c < nchunk; ++c) {
             cplx* Gk = Gc + (size_t)c * gsz;
-            long kb = k_begin + c * ORACLE_KCHUNK;
-            long ke = kb + ORACLE_KCHUNK;
+            long kb = k_begin + c * ORACLE_GRAD_KCHUNK;
+            long ke = kb + ORACLE_GRAD_KCHUNK;
             if (ke > k_begin + k_count) ke = k_begin + k_count;
             for (long f = kb; f < ke; ++f) {
                 long i0, i1, i2;
