@@ -123,6 +123,69 @@ def measure_batched(steps: int, warmup: int):
     return out
 
 
+def measure_large(adjoint: bool = True, parts: int = 16):
+    """The n_orb = 128 workload (729 R, 128^3 grid, 256 Fermi levels): the forward at
+    eta = 1e-3 and the adjoint at eta = 1e-2 over the whole grid, enqueued as `parts`
+    consecutive k-slabs (slabs add up exactly; each slab prints a progress line)."""
+    import torch
+
+    from paper_2309_06675_amd import kubo, synth
+
+    wl = synth.workload(4)
+    m = wl.models[0]
+    ef = fermi_levels(4, wl)
+    dev = "cuda:0"
+    t = kubo.to_device_t([m], dev)
+    efd = torch.from_numpy(ef).to(dev)
+    stream = torch.cuda.current_stream(dev)
+    cuts = [wl.n_k * i // parts for i in range(parts + 1)]
+    plans = [kubo.Plan([m], grid=wl.grid, n_fermi=wl.n_fermi, device=dev,
+                       slabs=[(cuts[i], cuts[i + 1] - cuts[i])]) for i in range(parts)]
+    warm = kubo.Plan([m], grid=wl.grid, n_fermi=wl.n_fermi, slabs=[(0, 4 * wl.grid[0])],
+                     device=dev)
+    warm.forward(t, efd, wl.eta, wl.kT)
+    warm.backward(t, efd, wl.eta_adjoint, wl.kT, torch.ones(1, wl.n_fermi, dtype=torch.float64,
+                                                            device=dev))
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        r = fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return r, a.elapsed_time(b)
+
+    sig = torch.zeros(1, wl.n_fermi, dtype=torch.float64, device=dev)
+    fms = 0.0
+    for i, p in enumerate(plans):
+        s_i, ms = timed(lambda: p.forward(t, efd, wl.eta, wl.kT))
+        assert p.device_status() == kubo.KUBO_OK
+        sig += s_i
+        fms += ms
+        print(f"large forward slab {i + 1}/{parts}: {ms:.1f} ms", file=sys.stderr, flush=True)
+    fpk = nominal_flops_per_k(m.n, m.n_R, wl.n_fermi, True)
+    out = {"workload": wl.name, "k_points": wl.n_k, "forward_ms": fms,
+           "forward_k_points_per_s": wl.n_k / (fms / 1e3),
+           "forward_frac_nominal": fpk * wl.n_k / (fms / 1e3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
+           "sigma_sum": float(sig.sum().item())}
+    if adjoint:
+        sbar = torch.ones(1, wl.n_fermi, dtype=torch.float64, device=dev)
+        g = torch.zeros_like(t)
+        bms = 0.0
+        for i, p in enumerate(plans):
+            g_i, ms = timed(lambda: p.backward(t, efd, wl.eta_adjoint, wl.kT, sbar))
+            assert p.device_status() == kubo.KUBO_OK
+            g += g_i
+            bms += ms
+            print(f"large adjoint slab {i + 1}/{parts}: {ms:.1f} ms", file=sys.stderr, flush=True)
+        out.update({"adjoint_ms": bms, "adjoint_k_points_per_s": wl.n_k / (bms / 1e3),
+                    "adjoint_forward_ratio": bms / fms,
+                    "grad_abs_sum": float(g.abs().sum().item())})
+    return out
+
+
 def kernel_source_digest() -> str:
     """sha256 of the sources of the dominant kernel (the one-wavefront per-k kernel)."""
     import hashlib
@@ -192,9 +255,17 @@ def main(argv=None):
                     help="timed steps of the 200-model batched workload (0 skips)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run one device copy of MB megabytes (counter calibration)")
+    ap.add_argument("--large", action="store_true",
+                    help="only run the n_orb = 128 workload (forward + adjoint) and print it")
     args = ap.parse_args(argv)
     if args.copy_calibration > 0:
         return copy_calibration(args.copy_calibration)
+    if args.large:
+        if args.gpus != 1:
+            print("bench.py measures one GPU", file=sys.stderr)
+            return 2
+        print(json.dumps(measure_large()), flush=True)
+        return 0
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(k-slabs shard across GPUs by design, but this build runs on one GPU only)",
