@@ -11,10 +11,14 @@
 //     rotations of a sweep are applied to Z afterwards, one row per lane, in a
 //     single streaming pass.
 //   * Back-transformation U = H_0 ... H_{n-2} Z: lane c owns column c.
-// Velocities: W = v U with v built on the fly from the pencil partial sums,
-// then U^+ W accumulated in registers, so A = U^+ v_x U and B = U^+ v_y U
-// never need their own LDS buffers; the curvature is taken straight from the
-// register tiles.
+// Velocities (n > 8): A = U^+ v_x U and B = U^+ v_y U are dense complex
+// products, done on the FP64 matrix cores (16x16x4 MFMA, four real products
+// per complex one).  v is staged in LDS, U is read once per k-point into the
+// MFMA operand layout and reused by both products of both velocities, and the
+// first product's accumulators feed the second directly (X = v U, then
+// M = X^+ U with the contraction index permuted so that every lane already
+// holds its operand).  The curvature is taken from the accumulator tiles.
+// For n <= 8: W = v U with v built on the fly, U^+ W accumulated in registers.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -49,6 +53,24 @@ __device__ __forceinline__ double lane_read(double v, int src) {
     const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), src);
     const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), src);
     return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// D = A B + C for a 16x4 (A) by 4x16 (B) FP64 tile.  Lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16]; D[l / 16 + 4 q][l % 16] is
+// element q of lane l's accumulator.
+__device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// sum over the 16 lanes of a DPP row (lanes 16r .. 16r+15); every lane gets it
+__device__ __forceinline__ double row16_sum(double v) {
+    v += __builtin_amdgcn_update_dpp(0.0, v, 0xB1, 0xF, 0xF, false);   // lane ^ 1
+    v += __builtin_amdgcn_update_dpp(0.0, v, 0x4E, 0xF, 0xF, false);   // lane ^ 2
+    v += __builtin_amdgcn_update_dpp(0.0, v, 0x141, 0xF, 0xF, false);  // 7 - lane within 8
+    v += __builtin_amdgcn_update_dpp(0.0, v, 0x140, 0xF, 0xF, false);  // 15 - lane within 16
+    return v;
 }
 
 template <int NP>
@@ -417,13 +439,176 @@ __device__ void wave_velocity(WaveLds<NP>& S, int n, int nR0, const double2* __r
     __syncthreads();
 }
 
-// Steps 1-3 at one k-point, one wavefront: E (S.E), U (S.U) and the register
-// tiles of A = U^+ v_x U and B = U^+ v_y U.  Returns false on QL non-convergence.
+// v (v_x if is_x, else v_y) into S.P, zero-padded to NP x NP:
+// v_il = sum_rho coef_rho T[rho][i][l], coef = e^{i k0 rho} (times i rho for v_x).
+// Lane-contiguous elements, so the pencil partial sums are read coalesced.
 template <int NP>
-__device__ bool wave_eigen_velocities(WaveLds<NP>& S, const ModelDev& md,
-                                      const double2* __restrict__ T0, const double2* __restrict__ T1,
-                                      const int* __restrict__ r0, int i0, int max_iter,
-                                      double2 (&Ma)[NP / 2], double2 (&Mb)[NP / 2]) {
+__device__ void wave_stage_velocity(WaveLds<NP>& S, int n, int nR0, const double2* __restrict__ T,
+                                    const int* __restrict__ r0, bool is_x) {
+    constexpr int LD = WaveLds<NP>::LD;
+    constexpr int PER = NP * NP / 64;
+    const int lane = threadIdx.x & 63;
+    const long long nn = (long long)n * n;
+    double2 acc[PER];
+    int off[PER];
+    bool valid[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = lane + 64 * q;
+        const int i = e / NP, l = e % NP;
+        valid[q] = (i < n) && (l < n);
+        off[q] = i * n + l;
+        acc[q] = c_make(0.0, 0.0);
+    }
+    for (int rho = 0; rho < nR0; ++rho) {
+        double2 cf = S.ph[rho];
+        if (is_x) cf = c_scale((double)r0[rho], c_i(cf));
+        const double2* Tr = T + (long long)rho * nn;
+#pragma unroll
+        for (int q = 0; q < PER; ++q)
+            if (valid[q]) acc[q] = c_fma(cf, Tr[off[q]], acc[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = lane + 64 * q;
+        S.P[(e / NP) * LD + (e % NP)] = acc[q];
+    }
+}
+
+// The U operands of both products: u[kt][s][tc] = U[16 kt + g + 4 s][16 tc + c],
+// g = lane / 16, c = lane % 16 (the B operand of k-step (kt, s) for column tile tc).
+template <int NP>
+__device__ void wave_load_uops(const WaveLds<NP>& S, double2 (&u)[NP / 16][4][NP / 16]) {
+    constexpr int LD = WaveLds<NP>::LD, NT = NP / 16;
+    const int lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
+#pragma unroll
+    for (int kt = 0; kt < NT; ++kt)
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int tc = 0; tc < NT; ++tc) u[kt][s][tc] = S.U[(16 * kt + g + 4 * s) * LD + 16 * tc + c16];
+}
+
+// M = U^+ v U from the staged v (S.P).  On return mr/mi[ti][tj][q] hold
+// Re/Im M[16 ti + g + 4 q][16 tj + c].
+//   X = v U:   k-step (kt, s) takes contraction index 16 kt + g + 4 s from lane group g;
+//   M = X^+ U: with the same contraction order, the A operand of lane l at
+//              k-step (kt, s) for row tile ti is conj(X[16 kt + g + 4 s][16 ti + c]),
+//              which is element s of the lane's own X tile (kt, ti).
+template <int NP>
+__device__ void wave_rotate_mfma(const WaveLds<NP>& S, const double2 (&u)[NP / 16][4][NP / 16],
+                                 v4d (&mr)[NP / 16][NP / 16], v4d (&mi)[NP / 16][NP / 16]) {
+    constexpr int LD = WaveLds<NP>::LD, NT = NP / 16;
+    const int lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
+    const v4d zero = {0.0, 0.0, 0.0, 0.0};
+    v4d xr[NT][NT], xi[NT][NT];
+#pragma unroll
+    for (int a = 0; a < NT; ++a)
+#pragma unroll
+        for (int b = 0; b < NT; ++b) {
+            xr[a][b] = zero;
+            xi[a][b] = zero;
+            mr[a][b] = zero;
+            mi[a][b] = zero;
+        }
+#pragma unroll
+    for (int kt = 0; kt < NT; ++kt) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            double2 a[NT];
+#pragma unroll
+            for (int tr = 0; tr < NT; ++tr) a[tr] = S.P[(16 * tr + c16) * LD + 16 * kt + g + 4 * s];
+            // (a_r + i a_i)(b_r + i b_i); independent accumulators back to back
+#pragma unroll
+            for (int tr = 0; tr < NT; ++tr)
+#pragma unroll
+                for (int tc = 0; tc < NT; ++tc) xr[tr][tc] = mfma16(a[tr].x, u[kt][s][tc].x, xr[tr][tc]);
+#pragma unroll
+            for (int tr = 0; tr < NT; ++tr)
+#pragma unroll
+                for (int tc = 0; tc < NT; ++tc) xi[tr][tc] = mfma16(a[tr].x, u[kt][s][tc].y, xi[tr][tc]);
+#pragma unroll
+            for (int tr = 0; tr < NT; ++tr)
+#pragma unroll
+                for (int tc = 0; tc < NT; ++tc) xr[tr][tc] = mfma16(-a[tr].y, u[kt][s][tc].y, xr[tr][tc]);
+#pragma unroll
+            for (int tr = 0; tr < NT; ++tr)
+#pragma unroll
+                for (int tc = 0; tc < NT; ++tc) xi[tr][tc] = mfma16(a[tr].y, u[kt][s][tc].x, xi[tr][tc]);
+        }
+    }
+    // (x_r - i x_i)(b_r + i b_i)
+#pragma unroll
+    for (int kt = 0; kt < NT; ++kt) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+#pragma unroll
+            for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < NT; ++tj) mr[ti][tj] = mfma16(xr[kt][ti][s], u[kt][s][tj].x, mr[ti][tj]);
+#pragma unroll
+            for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < NT; ++tj) mi[ti][tj] = mfma16(xr[kt][ti][s], u[kt][s][tj].y, mi[ti][tj]);
+#pragma unroll
+            for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < NT; ++tj) mr[ti][tj] = mfma16(xi[kt][ti][s], u[kt][s][tj].y, mr[ti][tj]);
+#pragma unroll
+            for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < NT; ++tj) mi[ti][tj] = mfma16(-xi[kt][ti][s], u[kt][s][tj].x, mi[ti][tj]);
+        }
+    }
+}
+
+// Omega_i = -2 sum_{j != i} Im(A_ij conj(B_ij)) g(E_i - E_j) into S.Om from the
+// accumulator tiles of A and B (row i = 16 ti + g + 4 q, column j = 16 tj + c).
+template <int NP>
+__device__ void wave_curvature_mfma(WaveLds<NP>& S, int n, double eta2,
+                                    const v4d (&ar)[NP / 16][NP / 16], const v4d (&ai)[NP / 16][NP / 16],
+                                    const v4d (&br)[NP / 16][NP / 16], const v4d (&bi)[NP / 16][NP / 16]) {
+    constexpr int NT = NP / 16;
+    const int lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
+    double om[NT][4];
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) om[ti][q] = 0.0;
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj) {
+        const int j = 16 * tj + c16;
+        const double ej = (j < n) ? S.E[j] : 0.0;
+#pragma unroll
+        for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = 16 * ti + g + 4 * q;
+                if (i < n && j < n && i != j) {
+                    const double de = S.E[i] - ej;
+                    const double den = de * de + eta2;
+                    if (den > 0.0) {
+                        const double qij = ai[ti][tj][q] * br[ti][tj][q] - ar[ti][tj][q] * bi[ti][tj][q];
+                        om[ti][q] += qij / den;
+                    }
+                }
+            }
+    }
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double tot = row16_sum(om[ti][q]);
+            const int i = 16 * ti + g + 4 * q;
+            if (c16 == 0 && i < n) S.Om[i] = -2.0 * tot;
+        }
+}
+
+// Steps 1-2 at one k-point, one wavefront: H(k), its eigenvalues (S.E) and
+// eigenvectors (S.U).  Returns false on QL non-convergence or non-finite values.
+template <int NP>
+__device__ bool wave_eigen(WaveLds<NP>& S, const ModelDev& md, const double2* __restrict__ T0,
+                           const int* __restrict__ r0, int i0, int max_iter) {
     constexpr int LD = WaveLds<NP>::LD;
     const int lane = threadIdx.x & 63;
     const int n = md.n;
@@ -484,8 +669,6 @@ __device__ bool wave_eigen_velocities(WaveLds<NP>& S, const ModelDev& md,
     if (__ballot(!ok) != 0ull) ok = false;
     __syncthreads();
     wave_backtransform<NP>(S, n);
-    wave_velocity<NP>(S, n, md.nR0, T0, r0, true, Ma);
-    wave_velocity<NP>(S, n, md.nR0, T1, r0, false, Mb);
     return ok;
 }
 
@@ -496,11 +679,16 @@ template <int NP>
 __global__ __launch_bounds__(64) void k_forward_wave(FwdLaunch a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     WaveLds<NP>& S = *reinterpret_cast<WaveLds<NP>*>(smem_raw);
+    constexpr int LD = WaveLds<NP>::LD;
     constexpr int HW = NP / 2;
+    constexpr int NT = NP / 16;
     const int lane = threadIdx.x & 63;
     const double eta2 = a.eta * a.eta;
     const int max_iter = a.max_sweeps >= kMaxSweeps ? 30 : 1;
     const double2* tbuf = reinterpret_cast<const double2*>(a.tbuf);
+    // U's padding (rows and columns n..NP-1) is never written below: keep it finite
+    for (int e = lane; e < NP * LD; e += 64) S.U[e] = c_make(0.0, 0.0);
+    __syncthreads();
     for (ItemSchedule sc = xcd_schedule(a.item_count); sc.next < sc.end; sc.next += sc.step) {
         const int item = sc.next;
         const BlockItem it = a.tb.blocks[a.item_begin + item];
@@ -513,30 +701,47 @@ __global__ __launch_bounds__(64) void k_forward_wave(FwdLaunch a) {
         const double* ef = a.e_fermi + md.f_off;
         double* part = a.partial + (long long)it.slot * a.nF;
         for (int kk = 0; kk < it.count; ++kk) {
-            double2 Ma[HW], Mb[HW];
-            const bool ok = wave_eigen_velocities<NP>(S, md, T0, T1, r0, it.i0 + kk, max_iter, Ma, Mb);
+            const bool ok = wave_eigen<NP>(S, md, T0, r0, it.i0 + kk, max_iter);
             if (!ok && lane == 0) atomicOr(a.status, kStatNoConv);
-            // Omega_i = -2 sum_{j != i} Im(A_ij B_ji) g(E_i - E_j), B_ji = conj(B_ij)
-            const int i = lane >> 1;
-            const int j0 = (lane & 1) * HW;
-            double om = 0.0;
-            if (i < n) {
-                const double ei = S.E[i];
+            if constexpr (NT >= 1) {
+                // A = U^+ v_x U, B = U^+ v_y U on the matrix cores
+                double2 u[NT][4][NT];
+                wave_load_uops<NP>(S, u);
+                wave_stage_velocity<NP>(S, n, md.nR0, T0, r0, true);
+                __syncthreads();
+                v4d ar[NT][NT], ai[NT][NT], br[NT][NT], bi[NT][NT];
+                wave_rotate_mfma<NP>(S, u, ar, ai);
+                __syncthreads();
+                wave_stage_velocity<NP>(S, n, md.nR0, T1, r0, false);
+                __syncthreads();
+                wave_rotate_mfma<NP>(S, u, br, bi);
+                wave_curvature_mfma<NP>(S, n, eta2, ar, ai, br, bi);
+            } else {
+                double2 Ma[HW], Mb[HW];
+                wave_velocity<NP>(S, n, md.nR0, T0, r0, true, Ma);
+                wave_velocity<NP>(S, n, md.nR0, T1, r0, false, Mb);
+                // Omega_i = -2 sum_{j != i} Im(A_ij B_ji) g(E_i - E_j), B_ji = conj(B_ij)
+                const int i = lane >> 1;
+                const int j0 = (lane & 1) * HW;
+                double om = 0.0;
+                if (i < n) {
+                    const double ei = S.E[i];
 #pragma unroll
-                for (int jj = 0; jj < HW; ++jj) {
-                    const int j = j0 + jj;
-                    if (j < n && j != i) {
-                        const double de = ei - S.E[j];
-                        const double den = de * de + eta2;
-                        if (den > 0.0) {
-                            const double q = Ma[jj].y * Mb[jj].x - Ma[jj].x * Mb[jj].y;
-                            om += q / den;
+                    for (int jj = 0; jj < HW; ++jj) {
+                        const int j = j0 + jj;
+                        if (j < n && j != i) {
+                            const double de = ei - S.E[j];
+                            const double den = de * de + eta2;
+                            if (den > 0.0) {
+                                const double q = Ma[jj].y * Mb[jj].x - Ma[jj].x * Mb[jj].y;
+                                om += q / den;
+                            }
                         }
                     }
                 }
+                om += __shfl_xor(om, 1, 64);
+                if (i < n && (lane & 1) == 0) S.Om[i] = -2.0 * om;
             }
-            om += __shfl_xor(om, 1, 64);
-            if (i < n && (lane & 1) == 0) S.Om[i] = -2.0 * om;
             __syncthreads();
             for (int j = lane; j < a.nF; j += 64) {
                 const double efj = ef[j];
@@ -548,6 +753,7 @@ __global__ __launch_bounds__(64) void k_forward_wave(FwdLaunch a) {
             __syncthreads();
         }
     }
+    (void)LD;
 }
 
 template <int NP>
