@@ -30,21 +30,46 @@
 
 namespace kubo {
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+// Cross-lane reductions without the LDS crossbar: DPP inside each row of 16
+// lanes, then the gfx950 row-swap instructions across rows and halves.  Every
+// lane ends with the same bits (each step combines the same two operands).
+__device__ __forceinline__ double dpp_xor1(double v) {
+    return __builtin_amdgcn_update_dpp(0.0, v, 0xB1, 0xF, 0xF, false);
+}
+
+__device__ __forceinline__ double join_u32(unsigned lo, unsigned hi) {
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+template <class Op>
+__device__ __forceinline__ double wave_allreduce(double v, Op op) {
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));   // lane ^ 1
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));   // lane ^ 2
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false));  // 7 - lane within 8
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false));  // 15 - lane within 16
+    {
+        const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+        const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)b, (unsigned)b, false, false);
+        const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+        v = op(join_u32(lo[0], hi[0]), join_u32(lo[1], hi[1]));  // rows (0, 1) and (2, 3)
+    }
+    {
+        const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+        const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)b, (unsigned)b, false, false);
+        const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+        v = op(join_u32(lo[0], hi[0]), join_u32(lo[1], hi[1]));  // the two halves
+    }
     return v;
 }
 
+__device__ __forceinline__ double wave_sum(double v) {
+    return wave_allreduce(v, [](double x, double y) { return x + y; });
+}
 __device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
-    return v;
+    return wave_allreduce(v, [](double x, double y) { return fmin(x, y); });
 }
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-    return v;
+    return wave_allreduce(v, [](double x, double y) { return fmax(x, y); });
 }
 
 // value of a per-lane register held by lane `src` (src must be wave-uniform)
@@ -79,6 +104,7 @@ struct WaveLds {
     double2 P[NP * LD];  // H, then the Householder vectors, then W = v U
     double2 U[NP * LD];  // Z (real parts) during QL, then U
     double2 tau[NP];
+    double2 vv[NP];
     double2 wv[NP];
     double cs[2 * NP];
     double2 de2[NP];  // (d_i, e_i) of the tridiagonal matrix, zero past n
@@ -88,23 +114,39 @@ struct WaveLds {
 };
 
 // Reduce the Hermitian matrix in S.P (n x n) to real tridiagonal form.
+// The matrix lives in registers: lane 2i + h holds row i, columns
+// [h NP/2, (h+1) NP/2).  Each step broadcasts the reflector v and the vector
+// w through LDS and applies A <- A - v w^+ - w v^+ in registers.
 // On return lane i holds d_i and e_i (e_{n-1} = 0); the Householder vector of
-// step k is stored in column k below the diagonal (row k+1 holds 1) and its
-// scalar in S.tau[k]; H = Q T Q^+ with Q = H_0 H_1 ... H_{n-2},
+// step k is stored in S.P column k below the diagonal (row k+1 holds 1) and
+// its scalar in S.tau[k]; H = Q T Q^+ with Q = H_0 H_1 ... H_{n-2},
 // H_k = I - tau_k v_k v_k^+.
 template <int NP>
 __device__ void wave_tridiag(WaveLds<NP>& S, int n, double& d_lane, double& e_lane) {
     constexpr int LD = WaveLds<NP>::LD;
-    const int r = threadIdx.x & 63;
+    constexpr int HW = NP / 2;
+    const int lane = threadIdx.x & 63;
+    const int i = lane >> 1, h = lane & 1, c0 = h * HW;
+    const bool row_ok = i < n;
+    double2 a[HW];
+#pragma unroll
+    for (int jj = 0; jj < HW; ++jj)
+        a[jj] = (row_ok && c0 + jj < n) ? S.P[i * LD + c0 + jj] : c_make(0.0, 0.0);
     d_lane = 0.0;
     e_lane = 0.0;
     for (int k = 0; k < n - 1; ++k) {
-        const bool act = (r > k) && (r < n);
-        const double2 x = act ? S.P[r * LD + k] : c_make(0.0, 0.0);
-        const double2 alpha = S.P[(k + 1) * LD + k];
-        const double dk = S.P[k * LD + k].x;
-        double xn2 = (act && r > k + 1) ? (x.x * x.x + x.y * x.y) : 0.0;
-        xn2 = wave_sum(xn2);
+        const int hk = k / HW, jk = k - hk * HW;  // half and slot holding column k
+        double2 xk = c_make(0.0, 0.0);
+#pragma unroll
+        for (int jj = 0; jj < HW; ++jj)
+            if (jj == jk) xk = a[jj];
+        const bool own = (h == hk);
+        const double2 xp = c_make(dpp_xor1(xk.x), dpp_xor1(xk.y));
+        const double2 x = own ? xk : xp;  // A[i][k] in both lanes of row i
+        const int src = 2 * (k + 1) + hk;
+        const double2 alpha = c_make(lane_read(xk.x, src), lane_read(xk.y, src));
+        const double dk = lane_read(xk.x, 2 * k + hk);
+        const double xn2 = wave_sum((own && i > k + 1 && i < n) ? (x.x * x.x + x.y * x.y) : 0.0);
         double beta;
         double2 tau, scal;
         if (xn2 == 0.0 && alpha.y == 0.0) {
@@ -120,39 +162,61 @@ __device__ void wave_tridiag(WaveLds<NP>& S, int n, double& d_lane, double& e_la
             const double den = 1.0 / (ar * ar + ai * ai);
             scal = c_make(ar * den, -ai * den);
         }
-        const double2 v = (r == k + 1) ? c_make(1.0, 0.0) : (act ? c_mul(x, scal) : c_make(0.0, 0.0));
-        if (r == k) {
+        double2 v = c_make(0.0, 0.0);
+        if (i == k + 1)
+            v = c_make(1.0, 0.0);
+        else if (i > k + 1 && i < n)
+            v = c_mul(x, scal);
+        if (lane == k) {
             d_lane = dk;
             e_lane = beta;
         }
-        __syncthreads();
-        if (act) S.P[r * LD + k] = v;
-        if (r == 0) S.tau[k] = tau;
+        // the reflector replaces column k below the diagonal
+#pragma unroll
+        for (int jj = 0; jj < HW; ++jj)
+            if (own && jj == jk && i > k) a[jj] = v;
+        if (lane == 0) S.tau[k] = tau;
+        if (h == 0 && i < NP) S.vv[i] = v;
         __syncthreads();
         if (tau.x == 0.0 && tau.y == 0.0) continue;
-        // p = A22 v (row r)
+        // p = A v (row i), the two halves combined within the lane pair
+        double2 vc[HW];
+#pragma unroll
+        for (int jj = 0; jj < HW; ++jj) vc[jj] = S.vv[c0 + jj];
         double2 p = c_make(0.0, 0.0);
-        if (act)
-            for (int c = k + 1; c < n; ++c) p = c_fma(S.P[r * LD + c], S.P[c * LD + k], p);
-        const double mu = wave_sum(act ? (v.x * p.x + v.y * p.y) : 0.0);  // v^+ p (real)
+#pragma unroll
+        for (int jj = 0; jj < HW; ++jj) p = c_fma(a[jj], vc[jj], p);
+        p = c_make(p.x + dpp_xor1(p.x), p.y + dpp_xor1(p.y));
+        const double mu = wave_sum(h == 0 ? (v.x * p.x + v.y * p.y) : 0.0);  // v^+ p (real)
         const double t2 = 0.5 * (tau.x * tau.x + tau.y * tau.y) * mu;
-        const double2 w = c_sub(c_mul(tau, p), c_scale(t2, v));
-        if (act) S.wv[r] = w;
+        double2 w = c_sub(c_mul(tau, p), c_scale(t2, v));
+        if (!(i > k && i < n)) w = c_make(0.0, 0.0);
+        if (h == 0 && i < NP) S.wv[i] = w;
         __syncthreads();
-        if (act) {
-            for (int c = k + 1; c < n; ++c) {
-                const double2 vc = S.P[c * LD + k], wc = S.wv[c];
-                double2 a = S.P[r * LD + c];
-                a = c_sub(a, c_add(c_mulc(v, wc), c_mulc(w, vc)));
-                S.P[r * LD + c] = a;
-            }
+        // A <- A - v w^+ - w v^+ (v_c = w_c = 0 for c <= k keeps the stored reflectors)
+#pragma unroll
+        for (int jj = 0; jj < HW; ++jj) {
+            const double2 wc = S.wv[c0 + jj];
+            a[jj] = c_sub(a[jj], c_add(c_mulc(v, wc), c_mulc(w, vc[jj])));
         }
         __syncthreads();
     }
-    if (r == n - 1) {
-        d_lane = S.P[(n - 1) * LD + (n - 1)].x;
-        e_lane = 0.0;
+    {
+        const int hl = (n - 1) / HW, jl = (n - 1) - hl * HW;
+        double2 last = c_make(0.0, 0.0);
+#pragma unroll
+        for (int jj = 0; jj < HW; ++jj)
+            if (jj == jl) last = a[jj];
+        const double dl = lane_read(last.x, 2 * (n - 1) + hl);
+        if (lane == n - 1) {
+            d_lane = dl;
+            e_lane = 0.0;
+        }
     }
+    // reflectors back to LDS for the back-transformation
+#pragma unroll
+    for (int jj = 0; jj < HW; ++jj)
+        if (row_ok && c0 + jj < i) S.P[i * LD + c0 + jj] = a[jj];
     __syncthreads();
 }
 
