@@ -366,17 +366,23 @@ __device__ double wave_bisect(const WaveLds<NP>& S, int n, double glo, double gh
 // Eigenvector of the tridiagonal matrix for an isolated eigenvalue lam by the
 // twisted factorisation of T - lam I: forward pivots dp, backward pivots dm,
 // twist index r = argmin |dp_r + dm_r - (d_r - lam)|, then z_r = 1 and the two
-// one-sided recurrences.  Returns the normalised vector in z[0..NP).
+// one-sided recurrences.  The lane keeps half `h` of the normalised vector:
+// u[jj] = z[h NP/2 + jj].
 template <int NP>
-__device__ void wave_twisted(const WaveLds<NP>& S, int n, double& lam, double pivmin,
-                             double (&z)[NP]) {
+__device__ void wave_twisted(const WaveLds<NP>& S, int n, double& lam, double pivmin, int h,
+                             double2 (&u)[NP / 2]) {
+    // 1/q: hardware estimate plus one Newton step (|q| >= pivmin keeps it finite)
+    auto rcp = [](double q) {
+        const double r = __builtin_amdgcn_rcp(q);
+        return fma(r, fma(-q, r, 1.0), r);
+    };
     double dp[NP], dm[NP];
     {
         double q = 1.0, e2prev = 0.0;
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
             const double2 de = S.de2[i];
-            double qi = (de.x - lam) - e2prev / q;
+            double qi = (de.x - lam) - e2prev * rcp(q);
             if (fabs(qi) < pivmin) qi = -pivmin;
             dp[i] = qi;
             q = qi;
@@ -388,7 +394,7 @@ __device__ void wave_twisted(const WaveLds<NP>& S, int n, double& lam, double pi
 #pragma unroll
         for (int i = NP - 1; i >= 0; --i) {
             const double2 de = S.de2[i];
-            double qi = (de.x - lam) - ((i < n - 1) ? de.y * de.y / q : 0.0);
+            double qi = (de.x - lam) - ((i < n - 1) ? de.y * de.y * rcp(q) : 0.0);
             if (fabs(qi) < pivmin) qi = -pivmin;
             dm[i] = qi;
             q = qi;
@@ -407,51 +413,63 @@ __device__ void wave_twisted(const WaveLds<NP>& S, int n, double& lam, double pi
             }
         }
     }
-#pragma unroll
-    for (int i = 0; i < NP; ++i) z[i] = (i == r) ? 1.0 : 0.0;
-    // below the twist: z_i = -(e_i / dp_i) z_{i+1}
+    // z_r = 1; below the twist z_i = -(e_i / dp_i) z_{i+1} (kept in dp_i),
+    // above it z_i = -(e_{i-1} / dm_i) z_{i-1} (kept in dm_i)
 #pragma unroll
     for (int i = NP - 2; i >= 0; --i) {
-        const double ei = S.de2[i].y;
-        const double v = -(ei / dp[i]) * z[i + 1];
-        if (i < r) z[i] = v;
+        const double zn = (i + 1 == r) ? 1.0 : dp[i + 1];
+        const double v = -(S.de2[i].y * rcp(dp[i])) * zn;
+        if (i < r) dp[i] = v;
     }
-    // above the twist: z_i = -(e_{i-1} / dm_i) z_{i-1}
 #pragma unroll
     for (int i = 1; i < NP; ++i) {
-        const double ei = S.de2[i - 1].y;
-        const double v = -(ei / dm[i]) * z[i - 1];
-        if (i > r && i < n) z[i] = v;
+        const double zp = (i - 1 == r) ? 1.0 : dm[i - 1];
+        const double v = -(S.de2[i - 1].y * rcp(dm[i])) * zp;
+        if (i > r) dm[i] = (i < n) ? v : 0.0;
     }
     double nrm = 0.0;
 #pragma unroll
-    for (int i = 0; i < NP; ++i) nrm += z[i] * z[i];
+    for (int i = 0; i < NP; ++i) {
+        const double zi = (i < r) ? dp[i] : ((i == r) ? 1.0 : dm[i]);
+        nrm += zi * zi;
+    }
     // (T - lam) z = gam e_r with z_r = 1: the Rayleigh quotient is lam + gam / |z|^2
     lam += gam / nrm;
     const double inv = 1.0 / sqrt(nrm);
 #pragma unroll
-    for (int i = 0; i < NP; ++i) z[i] *= inv;
+    for (int i = 0; i < NP; ++i) {
+        const double zi = (i < r) ? dp[i] : ((i == r) ? 1.0 : dm[i]);
+        if (i / (NP / 2) == h) u[i % (NP / 2)] = c_make(zi * inv, 0.0);
+    }
 }
 
-// U <- H_0 H_1 ... H_{n-2} U  (U holds Z on entry); lane c owns column c.
+// U <- H_0 H_1 ... H_{n-2} Z in registers: lane 2c + h holds rows
+// [h NP/2, (h+1) NP/2) of column c in u[] (Z on entry); the reflectors are
+// read from S.P (column k below the diagonal) as broadcasts.
 template <int NP>
-__device__ void wave_backtransform(WaveLds<NP>& S, int n) {
+__device__ void wave_backtransform(const WaveLds<NP>& S, int n, double2 (&u)[NP / 2]) {
     constexpr int LD = WaveLds<NP>::LD;
-    const int c = threadIdx.x & 63;
-    if (c < n) {
-        for (int k = n - 2; k >= 0; --k) {
-            const double2 tau = S.tau[k];
-            if (tau.x == 0.0 && tau.y == 0.0) continue;
-            double2 y = c_make(0.0, 0.0);
-            for (int r = k + 1; r < n; ++r) y = c_fmac(S.P[r * LD + k], S.U[r * LD + c], y);
-            const double2 ty = c_mul(tau, y);
-            for (int r = k + 1; r < n; ++r) {
-                const double2 vr = S.P[r * LD + k];
-                S.U[r * LD + c] = c_sub(S.U[r * LD + c], c_mul(vr, ty));
-            }
+    constexpr int HW = NP / 2;
+    const int lane = threadIdx.x & 63;
+    const int c0 = (lane & 1) * HW;
+    for (int k = n - 2; k >= 0; --k) {
+        const double2 tau = S.tau[k];
+        if (tau.x == 0.0 && tau.y == 0.0) continue;
+        double2 vr[HW];
+#pragma unroll
+        for (int jj = 0; jj < HW; ++jj) {
+            const int r = c0 + jj;
+            const double2 x = S.P[r * LD + k];
+            vr[jj] = (r > k && r < n) ? x : c_make(0.0, 0.0);
         }
+        double2 y = c_make(0.0, 0.0);  // v^+ u over this half of the column
+#pragma unroll
+        for (int jj = 0; jj < HW; ++jj) y = c_fmac(vr[jj], u[jj], y);
+        y = c_make(y.x + dpp_xor1(y.x), y.y + dpp_xor1(y.y));
+        const double2 ty = c_mul(tau, y);
+#pragma unroll
+        for (int jj = 0; jj < HW; ++jj) u[jj] = c_sub(u[jj], c_mul(vr[jj], ty));
     }
-    __syncthreads();
 }
 
 // M = U^+ v U for one velocity; lane (i = lane/2, half h) returns row i,
@@ -701,26 +719,26 @@ __device__ bool wave_eigen(WaveLds<NP>& S, const ModelDev& md, const double2* __
     const double emax = wave_max(lane < n ? fabs(e_lane) : 0.0);
     const double pivmin = 1e-290 * fmax(1.0, emax * emax);
     bool ok = true;
-    const double lam2 = wave_bisect<NP>(S, n, glo, ghi, pivmin);
-    const double lam = __shfl(lam2, 2 * lane, 64);  // lane j: eigenvalue j
-    const double lnext = __shfl_down(lam, 1, 64);
+    const double lam2 = wave_bisect<NP>(S, n, glo, ghi, pivmin);  // lanes 2j, 2j+1: eigenvalue j
+    constexpr int HW = NP / 2;
+    const int c = lane >> 1, h = lane & 1, c0 = h * HW;
+    const double lnext = __shfl_down(lam2, 2, 64);
     const double span = fmax(fabs(glo), fabs(ghi));
-    const bool close = (lane < n - 1) && (lnext - lam < 1e-3 * span);
+    const bool close = (c < n - 1) && (lnext - lam2 < 1e-3 * span);
+    double2 u[HW];
     // (the debug iteration cap sends every k-point through the iterative path)
     if (__ballot(close) == 0ull && max_iter > 1) {
-        // isolated eigenvalues: one twisted factorisation per lane
-        if (lane < n) {
-            double z[NP];
-            double lam_j = lam;
-            wave_twisted<NP>(S, n, lam_j, pivmin, z);
+        // isolated eigenvalues: one twisted factorisation per lane pair
 #pragma unroll
-            for (int i = 0; i < NP; ++i)
-                if (i < n) S.U[i * LD + lane] = c_make(z[i], 0.0);
-            S.E[lane] = lam_j;
-            if (!isfinite(lam_j)) ok = false;
+        for (int jj = 0; jj < HW; ++jj) u[jj] = c_make(0.0, 0.0);
+        if (c < n) {
+            double lam_c = lam2;
+            wave_twisted<NP>(S, n, lam_c, pivmin, h, u);
+            if (h == 0) S.E[c] = lam_c;
+            if (!isfinite(lam_c)) ok = false;
         }
     } else {
-        // a cluster: implicit QL with accumulated rotations
+        // a cluster: implicit QL with accumulated rotations (Z in S.U, lane = row)
         for (int e = lane; e < n * n; e += 64) {
             const int i = e / n, j = e - (e / n) * n;
             S.U[i * LD + j] = c_make(i == j ? 1.0 : 0.0, 0.0);
@@ -729,10 +747,22 @@ __device__ bool wave_eigen(WaveLds<NP>& S, const ModelDev& md, const double2* __
         ok = wave_ql<NP>(S, n, d_lane, e_lane, max_iter);
         if (lane < n) S.E[lane] = d_lane;
         if (__ballot(lane < n && !isfinite(d_lane)) != 0ull) ok = false;
+        __syncthreads();
+#pragma unroll
+        for (int jj = 0; jj < HW; ++jj) {
+            const int r = c0 + jj;
+            u[jj] = (c < n && r < n) ? c_make(S.U[r * LD + c].x, 0.0) : c_make(0.0, 0.0);
+        }
     }
     if (__ballot(!ok) != 0ull) ok = false;
+    wave_backtransform<NP>(S, n, u);
     __syncthreads();
-    wave_backtransform<NP>(S, n);
+#pragma unroll
+    for (int jj = 0; jj < HW; ++jj) {
+        const int r = c0 + jj;
+        if (c < n && r < n) S.U[r * LD + c] = u[jj];
+    }
+    __syncthreads();
     return ok;
 }
 
