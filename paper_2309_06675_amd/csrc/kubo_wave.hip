@@ -315,50 +315,72 @@ __device__ bool wave_ql(WaveLds<NP>& S, int n, double& d_lane, double& e_lane, i
     return ok;
 }
 
-// Eigenvalues of the real symmetric tridiagonal (d, e) in S.de2 by bisection.
-// Lanes 2j and 2j+1 search eigenvalue j (ascending): each step they count at
-// the two interior trisection points of [lo, hi] and keep the third that holds
-// eigenvalue j.  A fixed number of steps shrinks the Gershgorin interval below
-// 4 eps max|lambda|.  Returns lambda_j in both lanes.
+// Eigenvalues of the real symmetric tridiagonal (d, e) in S.de2 by Sturm-count
+// multisection.  Lanes 2j and 2j+1 search eigenvalue j (ascending): each step
+// they count at six interior points of [lo, hi] (three interleaved Sturm
+// sequences per lane, which hides the latency of the recurrence) and keep the
+// seventh that holds eigenvalue j.  A fixed number of steps shrinks the
+// Gershgorin interval below 4 eps max|lambda|.  Returns lambda_j in both lanes.
 template <int NP>
 __device__ double wave_bisect(const WaveLds<NP>& S, int n, double glo, double ghi, double pivmin) {
+    constexpr int NS = 3;  // points per lane
     const int lane = threadIdx.x & 63;
     const int j = lane >> 1;
     const int half = lane & 1;
+    // the matrix in registers; rows past n decouple (e = 0) and never count (d huge)
+    double dv[NP], e2v[NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        const double2 de = S.de2[i];
+        dv[i] = (i < n) ? de.x : 1e300;
+        e2v[i] = (i < n) ? de.y * de.y : 0.0;
+    }
     double lo = glo, hi = ghi;
     const double scale = fmax(fabs(glo), fabs(ghi));
     const double tol = 4.0 * 2.220446049250313e-16 * scale + 1e-300;
     int steps = 0;
-    for (double w = ghi - glo; w > tol && steps < 80; w *= (1.0 / 3.0)) ++steps;
+    for (double w = ghi - glo; w > tol && steps < 60; w *= (1.0 / 7.0)) ++steps;
     for (int it = 0; it < steps; ++it) {
-        const double third = (hi - lo) * (1.0 / 3.0);
-        const double x = half ? (hi - third) : (lo + third);
-        // Sturm count at x
-        int cnt = 0;
-        double q = 1.0, e2prev = 0.0;
-        for (int i = 0; i < n; ++i) {
-            const double2 de = S.de2[i];
-            // reciprocal estimate refined by one Newton step (full FP64 precision)
-            double rq = __builtin_amdgcn_rcp(q);
-            rq = fma(rq, fma(-q, rq, 1.0), rq);
-            double qi = (de.x - x) - e2prev * rq;
-            if (fabs(qi) < pivmin) qi = -pivmin;
-            cnt += (qi < 0.0) ? 1 : 0;
-            q = qi;
-            e2prev = de.y * de.y;
+        const double step = (hi - lo) * (1.0 / 7.0);
+        double x[NS], q[NS];
+        int cnt[NS];
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+            x[t] = lo + (double)(half * NS + t + 1) * step;
+            q[t] = 1.0;
+            cnt[t] = 0;
         }
-        const int cother = __shfl_xor(cnt, 1, 64);
-        const int c1 = half ? cother : cnt;  // count at lo + third
-        const int c2 = half ? cnt : cother;  // count at hi - third
-        const double x1 = lo + third, x2 = hi - third;
-        if (c1 > j) {
-            hi = x1;
-        } else if (c2 > j) {
-            lo = x1;
-            hi = x2;
-        } else {
-            lo = x2;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const double e2p = (i > 0) ? e2v[i - 1] : 0.0;
+#pragma unroll
+            for (int t = 0; t < NS; ++t) {
+                // reciprocal estimate refined by one Newton step (full FP64 precision)
+                double rq = __builtin_amdgcn_rcp(q[t]);
+                rq = fma(rq, fma(-q[t], rq, 1.0), rq);
+                double qi = fma(-e2p, rq, dv[i] - x[t]);
+                if (fabs(qi) < pivmin) qi = -pivmin;
+                cnt[t] += (qi < 0.0) ? 1 : 0;
+                q[t] = qi;
+            }
         }
+        // counts at the six points, ascending: this lane's and its partner's
+        int c[2 * NS];
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+            const int other = __builtin_amdgcn_update_dpp(0, cnt[t], 0xB1, 0xF, 0xF, false);
+            c[t] = half ? other : cnt[t];
+            c[NS + t] = half ? cnt[t] : other;
+        }
+        // eigenvalue j lies in [x_m, x_{m+1}) for the first point m+1 whose count exceeds j
+        int m = 2 * NS;
+#pragma unroll
+        for (int t = 2 * NS - 1; t >= 0; --t)
+            if (c[t] > j) m = t;
+        const double nlo = (m == 0) ? lo : lo + (double)m * step;
+        const double nhi = (m == 2 * NS) ? hi : lo + (double)(m + 1) * step;
+        lo = nlo;
+        hi = nhi;
     }
     return 0.5 * (lo + hi);
 }
