@@ -55,14 +55,16 @@ __device__ __forceinline__ double2 unit_phase2(long long a1, long long N1, long 
 }
 
 // Occupation: Fermi-Dirac at kT > 0, a step with f(E_F) = 1/2 at kT = 0.
+// One exponential of -|u| serves both signs (no divergent branch), and the
+// quotient uses a Newton-refined reciprocal.
 __device__ __forceinline__ double occupation(double e, double ef, double kT) {
     if (kT == 0.0) return e < ef ? 1.0 : (e > ef ? 0.0 : 0.5);
-    double u = (e - ef) / kT;
-    if (u > 0.0) {
-        double w = exp(-u);
-        return w / (1.0 + w);
-    }
-    return 1.0 / (1.0 + exp(u));
+    const double u = (e - ef) / kT;
+    const double w = exp(-fabs(u));
+    const double d = 1.0 + w;
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    return (u > 0.0) ? w * r : r;
 }
 
 // conj(a) * b  and  a * conj(b)

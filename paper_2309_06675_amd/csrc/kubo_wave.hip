@@ -719,14 +719,39 @@ __device__ bool wave_eigen(WaveLds<NP>& S, const ModelDev& md, const double2* __
     const long long nn = (long long)n * n;
     if (lane < md.nR0) S.ph[lane] = unit_phase((long long)i0 * r0[lane], md.N0);
     __syncthreads();
-    for (int e = lane; e < n * n; e += 64) {
-        const int i = e / n, j = e - (e / n) * n;
-        if (i > j) continue;
-        double2 h = c_make(0.0, 0.0);
-        for (int rho = 0; rho < md.nR0; ++rho) h = c_fma(T0[(long long)rho * nn + e], S.ph[rho], h);
-        if (i == j) h.y = 0.0;
-        S.P[i * LD + j] = h;
-        S.P[j * LD + i] = c_conj(h);
+    {
+        // upper triangle from the pencil partial sums (all loads of one rho in
+        // flight together), mirrored so that H is exactly Hermitian
+        constexpr int PER = NP * NP / 64;
+        double2 acc[PER];
+        int off[PER];
+        bool valid[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = lane + 64 * q;
+            const int i = e / NP, j = e % NP;
+            valid[q] = (i <= j) && (j < n);
+            off[q] = i * n + j;
+            acc[q] = c_make(0.0, 0.0);
+        }
+        for (int rho = 0; rho < md.nR0; ++rho) {
+            const double2 ph = S.ph[rho];
+            const double2* Tr = T0 + (long long)rho * nn;
+#pragma unroll
+            for (int q = 0; q < PER; ++q)
+                if (valid[q]) acc[q] = c_fma(Tr[off[q]], ph, acc[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            if (valid[q]) {
+                const int e = lane + 64 * q;
+                const int i = e / NP, j = e % NP;
+                double2 h = acc[q];
+                if (i == j) h.y = 0.0;
+                S.P[i * LD + j] = h;
+                S.P[j * LD + i] = c_conj(h);
+            }
+        }
     }
     __syncthreads();
     double d_lane, e_lane;

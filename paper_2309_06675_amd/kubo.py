@@ -217,6 +217,7 @@ class Plan:
         self.t_elems = sum(n * n * nr for n, nr in self.sizes)
         self.device = device
         self._ws = None
+        self._ws_stream = None
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -229,10 +230,18 @@ class Plan:
         return kubo_plan_info(self.handle)[1]
 
     def workspace(self):
+        """The plan's device workspace, allocated on first use on the current stream.
+        Use on another stream is recorded with the caching allocator, so the memory
+        is not handed out again before the work queued there has finished."""
         import torch
 
         if self._ws is None:
             self._ws = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=self.device)
+            self._ws_stream = torch.cuda.current_stream(self._ws.device)
+        else:
+            cur = torch.cuda.current_stream(self._ws.device)
+            if cur != self._ws_stream:
+                self._ws.record_stream(cur)
         return self._ws
 
     def _check_t(self, t):

@@ -180,11 +180,16 @@ def test_backward_graph_replay(torch):
     ef = torch.tensor([[-1.0, 0.5]], dtype=torch.float64, device="cuda")
     sb = torch.tensor([[0.7, 1.0]], dtype=torch.float64, device="cuda")
     t = kubo.to_device_t([m])
-    ref = kubo.Plan([m], grid=grid, n_fermi=2).backward(t, ef, 0.02, 0.02, sb)
+    # keep the eager plan (and its workspace) alive until its kernels are done:
+    # a freed workspace can be handed out again on the default stream and
+    # written from another stream while those kernels still read it
+    eager = kubo.Plan([m], grid=grid, n_fermi=2)
+    ref = eager.backward(t, ef, 0.02, 0.02, sb)
+    torch.cuda.synchronize()
     g = kubo.Plan([m], grid=grid, n_fermi=2, flags=kubo.KUBO_F_GRAPH)
     s = torch.cuda.Stream()
-    out = torch.empty_like(t)
     with torch.cuda.stream(s):
+        out = torch.empty_like(t)
         for rep in range(3):
             out.fill_(complex(float("nan"), 0.0))
             g.backward(t, ef, 0.02, 0.02, sb, out=out)
