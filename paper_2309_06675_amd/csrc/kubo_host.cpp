@@ -556,7 +556,12 @@ kubo_status enqueue_backward(kubo_plan_s* P, const double* t, const double* ef, 
             L.item_count = c.cls[k].count;
             L.max_groups = P->wg_groups;
             TimedScope ts(P, s, 1, c.cls_kpts[k]);
-            HIP_TRY(launch_adjoint_wg(L, s));
+            if (kClasses[k].wave) {
+                L.max_groups = P->max_groups;
+                HIP_TRY(launch_adjoint_wave(L, kClasses[k].np, s));
+            } else {
+                HIP_TRY(launch_adjoint_wg(L, s));
+            }
             ts.finish();
         }
         HIP_TRY(launch_gacc(tb, tb.granges, c.grange_begin, c.grange_count, P->max_nR, P->max_nn,

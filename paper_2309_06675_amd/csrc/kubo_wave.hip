@@ -110,6 +110,8 @@ struct WaveLds {
     double2 de2[NP];  // (d_i, e_i) of the tridiagonal matrix, zero past n
     double E[NP];
     double Om[NP];
+    double phi[NP];   // adjoint: phi(E_b) = sum_j sbar_j f_j(E_b)
+    double dphi[NP];  // and its derivative
     double2 ph[16];
 };
 
@@ -924,6 +926,457 @@ hipError_t launch_forward_wave(const FwdLaunch& L, hipStream_t s) {
         default:
             return hipErrorInvalidValue;
     }
+}
+
+// ---------------------------------------------------------------------------
+// k_adjoint_wave: reverse mode of steps 1-4 for one k-point per wavefront
+// (n <= NP <= 32), every dense product on the matrix cores.  For
+// L = sum_j sbar_j sigma_j and phi(E) = sum_j sbar_j f_j(E):
+//   K_mq  = (phi_m - phi_q) g(E_m - E_q)          (real, antisymmetric)
+//   Abar  = (i/N) K o B,  Bbar = -(i/N) K o A     (Hermitian)
+//   D     = (K o B) A - (K o A) B,  X = (i/N)(D + D^+) = [Abar, A] + [Bbar, B]
+//   Hbar' = X_mq / (E_m - E_q) off the diagonal; on the diagonal and for
+//           pairs closer than delta, the divided-difference limit
+//           (i/N) sum_p dK(x, E_p)/dx at x = (E_m + E_q)/2 (B_mp A_pq - A_mp B_pq)
+//   Hbar  = U Hbar' U^+,  vbar_x = U Abar U^+,  vbar_y = U Bbar U^+
+// and the block's pencil partials PH_rho += e^{-i k0 rho}(Hbar - i rho vbar_x),
+// PY_rho += e^{-i k0 rho} vbar_y.  Every matrix is held in the accumulator
+// layout: element q of lane l's tile (ti, tj) is M[16 ti + g + 4 q][16 tj + c].
+// ---------------------------------------------------------------------------
+
+// f(x) and f'(x) summed against sbar: one exponential per Fermi level
+__device__ __forceinline__ void wave_phi_at(double x, const double* __restrict__ ef,
+                                            const double* __restrict__ sb, int nF, double kT,
+                                            double& phi, double& dphi) {
+    double p = 0.0, d = 0.0;
+    for (int j = 0; j < nF; ++j) {
+        if (kT > 0.0) {
+            const double u = (x - ef[j]) / kT;
+            const double w = exp(-fabs(u));
+            const double dd = 1.0 + w;
+            double r = __builtin_amdgcn_rcp(dd);
+            r = fma(r, fma(-dd, r, 1.0), r);
+            const double f = (u > 0.0) ? w * r : r;
+            p += sb[j] * f;
+            d -= sb[j] * (w * r * r) / kT;  // f (1 - f) / kT = w / (1 + w)^2 / kT
+        } else {
+            p += sb[j] * occupation(x, ef[j], kT);
+        }
+    }
+    phi = p;
+    dphi = d;
+}
+
+// R = U M U^+ for Hermitian M (accumulator layout), with
+// ua[kt][s][tr] = U[16 tr + c][16 kt + g + 4 s]:
+//   Q = M U^+: A operand M[16 tr + c][kappa] = conj(M[kappa][16 tr + c]) (own element),
+//              B operand conj(U[16 tc + c][kappa]) = conj(ua);
+//   R = U Q:   A operand ua, B operand Q[kappa][16 tc + c] (own element).
+template <int NP>
+__device__ void wave_sandwich(const v4d (&mr)[NP / 16][NP / 16], const v4d (&mi)[NP / 16][NP / 16],
+                              const double2 (&ua)[NP / 16][4][NP / 16], v4d (&rr)[NP / 16][NP / 16],
+                              v4d (&ri)[NP / 16][NP / 16]) {
+    constexpr int NT = NP / 16;
+    const v4d zero = {0.0, 0.0, 0.0, 0.0};
+    v4d qr[NT][NT], qi[NT][NT];
+#pragma unroll
+    for (int a = 0; a < NT; ++a)
+#pragma unroll
+        for (int b = 0; b < NT; ++b) {
+            qr[a][b] = zero;
+            qi[a][b] = zero;
+            rr[a][b] = zero;
+            ri[a][b] = zero;
+        }
+    // Q = M U^+: (x_r - i x_i)(u_r - i u_i) with x = M[kappa][16 tr + c], u = U[16 tc + c][kappa]
+#pragma unroll
+    for (int kt = 0; kt < NT; ++kt) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+#pragma unroll
+            for (int tr = 0; tr < NT; ++tr)
+#pragma unroll
+                for (int tc = 0; tc < NT; ++tc) qr[tr][tc] = mfma16(mr[kt][tr][s], ua[kt][s][tc].x, qr[tr][tc]);
+#pragma unroll
+            for (int tr = 0; tr < NT; ++tr)
+#pragma unroll
+                for (int tc = 0; tc < NT; ++tc) qi[tr][tc] = mfma16(-mr[kt][tr][s], ua[kt][s][tc].y, qi[tr][tc]);
+#pragma unroll
+            for (int tr = 0; tr < NT; ++tr)
+#pragma unroll
+                for (int tc = 0; tc < NT; ++tc) qr[tr][tc] = mfma16(-mi[kt][tr][s], ua[kt][s][tc].y, qr[tr][tc]);
+#pragma unroll
+            for (int tr = 0; tr < NT; ++tr)
+#pragma unroll
+                for (int tc = 0; tc < NT; ++tc) qi[tr][tc] = mfma16(-mi[kt][tr][s], ua[kt][s][tc].x, qi[tr][tc]);
+        }
+    }
+    // R = U Q: (u_r + i u_i)(q_r + i q_i) with u = U[16 tr + c][kappa], q = Q[kappa][16 tc + c]
+#pragma unroll
+    for (int kt = 0; kt < NT; ++kt) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+#pragma unroll
+            for (int tr = 0; tr < NT; ++tr)
+#pragma unroll
+                for (int tc = 0; tc < NT; ++tc) rr[tr][tc] = mfma16(ua[kt][s][tr].x, qr[kt][tc][s], rr[tr][tc]);
+#pragma unroll
+            for (int tr = 0; tr < NT; ++tr)
+#pragma unroll
+                for (int tc = 0; tc < NT; ++tc) ri[tr][tc] = mfma16(ua[kt][s][tr].x, qi[kt][tc][s], ri[tr][tc]);
+#pragma unroll
+            for (int tr = 0; tr < NT; ++tr)
+#pragma unroll
+                for (int tc = 0; tc < NT; ++tc) rr[tr][tc] = mfma16(-ua[kt][s][tr].y, qi[kt][tc][s], rr[tr][tc]);
+#pragma unroll
+            for (int tr = 0; tr < NT; ++tr)
+#pragma unroll
+                for (int tc = 0; tc < NT; ++tc) ri[tr][tc] = mfma16(ua[kt][s][tr].y, qr[kt][tc][s], ri[tr][tc]);
+        }
+    }
+}
+
+template <int NP>
+__global__ __launch_bounds__(64) void k_adjoint_wave(WgLaunch a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    WaveLds<NP>& S = *reinterpret_cast<WaveLds<NP>*>(smem_raw);
+    constexpr int LD = WaveLds<NP>::LD;
+    constexpr int NT = NP / 16;
+    static_assert(NT >= 1, "the matrix-core adjoint needs NP >= 16");
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 4, c16 = lane & 15;
+    const double eta2 = a.eta * a.eta;
+    const double scl = (a.kT > 0.0) ? fmin(a.eta, a.kT) : a.eta;
+    const double delta = 1e-5 * scl;
+    const int max_iter = a.max_iter >= kMaxSweeps ? 30 : 1;
+    const double2* tbuf = reinterpret_cast<const double2*>(a.tbuf);
+    double2* pbuf = reinterpret_cast<double2*>(a.pbuf);
+    const v4d zero = {0.0, 0.0, 0.0, 0.0};
+    for (int e = lane; e < NP * LD; e += 64) S.U[e] = c_make(0.0, 0.0);
+    __syncthreads();
+    for (ItemSchedule sc = xcd_schedule(a.item_count); sc.next < sc.end; sc.next += sc.step) {
+        const int item = sc.next;
+        const BlockItem it = a.tb.blocks[a.item_begin + item];
+        const ModelDev md = a.tb.models[it.model];
+        const int n = md.n;
+        const long long nn = (long long)n * n;
+        const double2* T0 = tbuf + it.tbuf_off;
+        const double2* T1 = T0 + (long long)md.nR0 * nn;
+        double2* PH = pbuf + it.pbuf_off;
+        double2* PY = PH + (long long)md.nR0 * nn;
+        const int* r0 = a.tb.r0val + md.r0_first;
+        const double* ef = a.e_fermi + md.f_off;
+        const double* sb = a.sbar + md.f_off;
+        const double invN = 1.0 / (double)md.Nk;
+        for (int kk = 0; kk < it.count; ++kk) {
+            // ---- recompute: E, U, A = U^+ v_x U, B = U^+ v_y U
+            const bool ok = wave_eigen<NP>(S, md, T0, r0, it.i0 + kk, max_iter);
+            if (!ok && lane == 0) atomicOr(a.status, kStatNoConv);
+            v4d ar[NT][NT], ai[NT][NT], br[NT][NT], bi[NT][NT];
+            {
+                double2 u[NT][4][NT];
+                wave_load_uops<NP>(S, u);
+                wave_stage_velocity<NP>(S, n, md.nR0, T0, r0, true);
+                __syncthreads();
+                wave_rotate_mfma<NP>(S, u, ar, ai);
+                __syncthreads();
+                wave_stage_velocity<NP>(S, n, md.nR0, T1, r0, false);
+                __syncthreads();
+                wave_rotate_mfma<NP>(S, u, br, bi);
+            }
+            // ---- phi, phi' at the bands (lane pair per band, halves of the levels summed)
+            {
+                const int b = lane >> 1, h = lane & 1;
+                double p = 0.0, d = 0.0;
+                if (b < n) {
+                    const int half = (a.nF + 1) / 2;
+                    const int j0 = h * half, j1 = (h == 0) ? half : a.nF;
+                    wave_phi_at(S.E[b], ef + j0, sb + j0, j1 - j0, a.kT, p, d);
+                }
+                p += dpp_xor1(p);
+                d += dpp_xor1(d);
+                if (b < n && h == 0) {
+                    S.phi[b] = p;
+                    S.dphi[b] = d;
+                }
+            }
+            __syncthreads();
+            // ---- K on this lane's elements
+            double K[NT][NT][4];
+#pragma unroll
+            for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int m = 16 * ti + g + 4 * q, c = 16 * tj + c16;
+                        double kv = 0.0;
+                        if (m < n && c < n && m != c) {
+                            const double de = S.E[m] - S.E[c];
+                            kv = (S.phi[m] - S.phi[c]) / (de * de + eta2);
+                        }
+                        K[ti][tj][q] = kv;
+                    }
+            // ---- D = (K o B) A - (K o A) B.  A operand at k-step (kt, s), row tile tr:
+            // (K o B)[16 tr + c][kappa] = -K[kappa][..] conj(B[kappa][16 tr + c]) (own element)
+            v4d dr[NT][NT], di[NT][NT];
+#pragma unroll
+            for (int x = 0; x < NT; ++x)
+#pragma unroll
+                for (int y = 0; y < NT; ++y) {
+                    dr[x][y] = zero;
+                    di[x][y] = zero;
+                }
+#pragma unroll
+            for (int kt = 0; kt < NT; ++kt) {
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    double zr[NT], zi[NT], wr[NT], wi[NT];
+#pragma unroll
+                    for (int tr = 0; tr < NT; ++tr) {
+                        const double kv = K[kt][tr][s];
+                        zr[tr] = -kv * br[kt][tr][s];
+                        zi[tr] = kv * bi[kt][tr][s];
+                        wr[tr] = kv * ar[kt][tr][s];  // minus sign of -(K o A) folded in
+                        wi[tr] = -kv * ai[kt][tr][s];
+                    }
+#pragma unroll
+                    for (int tr = 0; tr < NT; ++tr)
+#pragma unroll
+                        for (int tc = 0; tc < NT; ++tc) {
+                            // (z_r + i z_i)(a_r + i a_i) + (w_r + i w_i)(b_r + i b_i)
+                            dr[tr][tc] = mfma16(zr[tr], ar[kt][tc][s], dr[tr][tc]);
+                            di[tr][tc] = mfma16(zr[tr], ai[kt][tc][s], di[tr][tc]);
+                            dr[tr][tc] = mfma16(-zi[tr], ai[kt][tc][s], dr[tr][tc]);
+                            di[tr][tc] = mfma16(zi[tr], ar[kt][tc][s], di[tr][tc]);
+                            dr[tr][tc] = mfma16(wr[tr], br[kt][tc][s], dr[tr][tc]);
+                            di[tr][tc] = mfma16(wr[tr], bi[kt][tc][s], di[tr][tc]);
+                            dr[tr][tc] = mfma16(-wi[tr], bi[kt][tc][s], dr[tr][tc]);
+                            di[tr][tc] = mfma16(wi[tr], br[kt][tc][s], di[tr][tc]);
+                        }
+                }
+            }
+            // ---- X = (i/N)(D + D^+) via a transpose through S.P; Hbar' = X / (E_m - E_q)
+#pragma unroll
+            for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        S.P[(16 * ti + g + 4 * q) * LD + 16 * tj + c16] = c_make(dr[ti][tj][q], di[ti][tj][q]);
+            __syncthreads();
+            v4d hr[NT][NT], hi[NT][NT];
+            double dsum[NT][4];
+#pragma unroll
+            for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) dsum[ti][q] = 0.0;
+            bool any_near = false;
+#pragma unroll
+            for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int m = 16 * ti + g + 4 * q, c = 16 * tj + c16;
+                        const double2 dt = S.P[c * LD + m];
+                        double vr = 0.0, vi = 0.0;
+                        if (m < n && c < n) {
+                            const double de = S.E[m] - S.E[c];
+                            // diagonal: Ebar_m = -(2/N) sum_p dK(E_m, E_p) Im(B_mp conj(A_mp))
+                            const double x = de;
+                            const double den = x * x + eta2;
+                            const double w = S.dphi[m] / den - (S.phi[m] - S.phi[c]) * 2.0 * x / (den * den);
+                            // (the p = m term, B_mm A_mm - A_mm B_mm, is exactly zero)
+                            const double im = bi[ti][tj][q] * ar[ti][tj][q] - br[ti][tj][q] * ai[ti][tj][q];
+                            if (m != c) dsum[ti][q] += w * im;
+                            if (m != c) {
+                                if (fabs(de) >= delta) {
+                                    // (i/N)(D_mc + conj(D_cm)) / de
+                                    const double sr = dr[ti][tj][q] + dt.x, si = di[ti][tj][q] - dt.y;
+                                    const double f = invN / de;
+                                    vr = -si * f;
+                                    vi = sr * f;
+                                } else {
+                                    any_near = true;
+                                }
+                            }
+                        }
+                        hr[ti][tj][q] = vr;
+                        hi[ti][tj][q] = vi;
+                    }
+            // diagonal from the row sums (the 16 lanes of a row hold its column slices)
+#pragma unroll
+            for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const double tot = row16_sum(dsum[ti][q]);
+                    const int m = 16 * ti + g + 4 * q;
+                    if (c16 == ((g + 4 * q) & 15)) hr[ti][ti][q] = (m < n) ? -2.0 * invN * tot : 0.0;
+                }
+            // U operands of the back-rotations: ua[kt][s][tr] = U[16 tr + c][16 kt + g + 4 s]
+            double2 ua[NT][4][NT];
+#pragma unroll
+            for (int kt = 0; kt < NT; ++kt)
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+#pragma unroll
+                    for (int tr = 0; tr < NT; ++tr) ua[kt][s][tr] = S.U[(16 * tr + c16) * LD + 16 * kt + g + 4 * s];
+            __syncthreads();
+            // near-degenerate pairs: the divided-difference limit, from A and B staged in LDS
+            if (__ballot(any_near) != 0ull) {
+#pragma unroll
+                for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int idx = (16 * ti + g + 4 * q) * LD + 16 * tj + c16;
+                            S.P[idx] = c_make(ar[ti][tj][q], ai[ti][tj][q]);
+                            S.U[idx] = c_make(br[ti][tj][q], bi[ti][tj][q]);
+                        }
+                __syncthreads();
+#pragma unroll
+                for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int m = 16 * ti + g + 4 * q, c = 16 * tj + c16;
+                            if (m < n && c < n && m != c && fabs(S.E[m] - S.E[c]) < delta) {
+                                const double xm = 0.5 * (S.E[m] + S.E[c]);
+                                double phx, dphx;
+                                wave_phi_at(xm, ef, sb, a.nF, a.kT, phx, dphx);
+                                double2 acc = c_make(0.0, 0.0);
+                                for (int p = 0; p < n; ++p) {
+                                    const double x = xm - S.E[p];
+                                    const double den = x * x + eta2;
+                                    const double w = dphx / den - (phx - S.phi[p]) * 2.0 * x / (den * den);
+                                    double2 z = c_mul(S.U[m * LD + p], S.P[p * LD + c]);
+                                    z = c_sub(z, c_mul(S.P[m * LD + p], S.U[p * LD + c]));
+                                    acc = c_add(acc, c_scale(w, z));
+                                }
+                                acc = c_scale(invN, c_i(acc));
+                                hr[ti][tj][q] = acc.x;
+                                hi[ti][tj][q] = acc.y;
+                            }
+                        }
+                __syncthreads();
+            }
+            // ---- Abar = (i/N) K o B (registers); Bbar = -(i/N) K o A parked in S.U
+            // (U itself is in ua now; the padding of both stays zero)
+            v4d xr[NT][NT], xi[NT][NT];
+#pragma unroll
+            for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const double kv = invN * K[ti][tj][q];
+                        xr[ti][tj][q] = -kv * bi[ti][tj][q];
+                        xi[ti][tj][q] = kv * br[ti][tj][q];
+                        S.U[(16 * ti + g + 4 * q) * LD + 16 * tj + c16] =
+                            c_make(kv * ai[ti][tj][q], -kv * ar[ti][tj][q]);
+                    }
+            // ---- vbar_x = U Abar U^+ (parked in S.P), Hbar = U Hbar' U^+ -> PH
+            {
+                v4d vr_[NT][NT], vi_[NT][NT];
+                wave_sandwich<NP>(xr, xi, ua, vr_, vi_);
+#pragma unroll
+                for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            S.P[(16 * ti + g + 4 * q) * LD + 16 * tj + c16] = c_make(vr_[ti][tj][q], vi_[ti][tj][q]);
+            }
+            bool bad = false;
+            {
+                v4d hbr[NT][NT], hbi[NT][NT];
+                wave_sandwich<NP>(hr, hi, ua, hbr, hbi);
+                for (int rho = 0; rho < md.nR0; ++rho) {
+                    const double2 pc = c_conj(S.ph[rho]);
+                    const double rr = (double)r0[rho];
+                    double2* ph_ = PH + (long long)rho * nn;
+#pragma unroll
+                    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+                        for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) {
+                                const int m = 16 * ti + g + 4 * q, c = 16 * tj + c16;
+                                if (m < n && c < n) {
+                                    // Hbar - i rho vbar_x
+                                    const double2 vx = S.P[m * LD + c];
+                                    const double2 w = c_make(hbr[ti][tj][q] + rr * vx.y, hbi[ti][tj][q] - rr * vx.x);
+                                    const double2 h1 = c_mul(pc, w);
+                                    bad |= !isfinite(h1.x + h1.y);
+                                    const long long e = (long long)m * n + c;
+                                    ph_[e] = (kk == 0) ? h1 : c_add(ph_[e], h1);
+                                }
+                            }
+                }
+            }
+            // ---- vbar_y = U Bbar U^+ -> PY
+            {
+                v4d yr[NT][NT], yi[NT][NT];
+#pragma unroll
+                for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const double2 v = S.U[(16 * ti + g + 4 * q) * LD + 16 * tj + c16];
+                            yr[ti][tj][q] = v.x;
+                            yi[ti][tj][q] = v.y;
+                        }
+                v4d vyr[NT][NT], vyi[NT][NT];
+                wave_sandwich<NP>(yr, yi, ua, vyr, vyi);
+                for (int rho = 0; rho < md.nR0; ++rho) {
+                    const double2 pc = c_conj(S.ph[rho]);
+                    double2* py_ = PY + (long long)rho * nn;
+#pragma unroll
+                    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+                        for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) {
+                                const int m = 16 * ti + g + 4 * q, c = 16 * tj + c16;
+                                if (m < n && c < n) {
+                                    const double2 y1 = c_mul(pc, c_make(vyr[ti][tj][q], vyi[ti][tj][q]));
+                                    bad |= !isfinite(y1.x + y1.y);
+                                    const long long e = (long long)m * n + c;
+                                    py_[e] = (kk == 0) ? y1 : c_add(py_[e], y1);
+                                }
+                            }
+                }
+            }
+            if (__ballot(bad) != 0ull && lane == 0) atomicOr(a.status, kStatNonFinite);
+            __syncthreads();
+        }
+    }
+}
+
+template <int NP>
+static hipError_t launch_adjoint_wave_t(const WgLaunch& L, hipStream_t s) {
+    const size_t lds = sizeof(WaveLds<NP>);
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_adjoint_wave<NP>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    const int grid = L.item_count < L.max_groups ? L.item_count : L.max_groups;
+    hipLaunchKernelGGL((k_adjoint_wave<NP>), dim3(grid), dim3(64), lds, s, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_wave(const WgLaunch& L, int np, hipStream_t s) {
+    if (L.item_count <= 0) return hipSuccess;
+    if (np <= 16) return launch_adjoint_wave_t<16>(L, s);
+    if (np <= 32) return launch_adjoint_wave_t<32>(L, s);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace kubo
