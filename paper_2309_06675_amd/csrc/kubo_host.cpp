@@ -160,7 +160,8 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
     // per model: tables and its pencils / blocks (in model order)
     struct PB {
         PencilItem pi;
-        std::vector<BlockItem> blocks;
+        std::vector<BlockItem> blocks;   // forward k-blocks (the tile's k_block)
+        std::vector<BlockItem> bblocks;  // backward k-blocks: longer, so fewer pencil partials
         size_t tbytes, pbytes;
         int cls;
     };
@@ -214,6 +215,10 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
         int kblock = std::min(d.grid[0], 32);
         auto ti = tile_of.find(d.n_orb);
         if (ti != tile_of.end()) kblock = std::min(d.grid[0], ti->second.k_block);
+        // the backward writes one set of pencil partials per k-block and sums them
+        // afterwards, so it takes blocks of about 32 points, balanced over the pencil
+        const int nbb = (d.grid[0] + 31) / 32;
+        const int kblock_b = std::max(kblock, (d.grid[0] + nbb - 1) / nbb);
         int cls = class_of(d.n_orb);
         if (ti != tile_of.end() && ti->second.threads == 256) cls = kNumClasses - 1;
         md.slot_first = slot;
@@ -241,7 +246,17 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
                     bi.i2 = pb.pi.i2;
                     pb.blocks.push_back(bi);
                 }
-                pb.pbytes = mat_bytes * pb.blocks.size();
+                for (long long a = a0; a < a1; a += kblock_b) {
+                    BlockItem bi{};
+                    bi.model = m;
+                    bi.i0 = (int)a;
+                    bi.count = (int)std::min<long long>(kblock_b, a1 - a);
+                    bi.slot = -1;  // no forward partial sums
+                    bi.i1 = pb.pi.i1;
+                    bi.i2 = pb.pi.i2;
+                    pb.bblocks.push_back(bi);
+                }
+                pb.pbytes = mat_bytes * pb.bblocks.size();
                 all.push_back(std::move(pb));
             }
         }
@@ -253,7 +268,8 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
     P->t_elems = t_off;
     P->n_slots = slot;
 
-    // chunks: consecutive pencils while the T (and, backward, P) regions stay under the cap
+    // chunks: consecutive pencils while the T region stays under the cap (and, backward,
+    // the per-block pencil partials under four times the cap)
     auto chunkify = [&](bool with_p, kubo_plan_s::ChunkSet& cs) {
         Chunk cur;
         std::vector<std::vector<BlockItem>> cls_blocks(kNumClasses);
@@ -303,16 +319,16 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
         for (const auto& pb0 : all) {
             PB pb = pb0;
             if (cur.pencil_count > 0 &&
-                (cur.tbytes + pb.tbytes > cap || (with_p && cur.pbytes + pb.pbytes > cap)))
+                (cur.tbytes + pb.tbytes > cap || (with_p && cur.pbytes + pb.pbytes > 4 * cap)))
                 flush();
             PencilItem pi = pb.pi;
             pi.tbuf_off = (long long)(cur.tbytes / 16);
             long long poff = (long long)(cur.pbytes / 16);
             const long long mat = (long long)(pb.tbytes / 16);
-            for (auto& b : pb.blocks) {
+            for (auto& b : (with_p ? pb.bblocks : pb.blocks)) {
                 b.tbuf_off = pi.tbuf_off;
-                b.pbuf_off = poff;
-                poff += mat;
+                b.pbuf_off = with_p ? poff : 0;
+                if (with_p) poff += mat;
                 cls_blocks[pb.cls].push_back(b);
             }
             cs.pencils.push_back(pi);
