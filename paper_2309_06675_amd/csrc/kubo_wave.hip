@@ -712,9 +712,13 @@ __device__ void wave_curvature_mfma(WaveLds<NP>& S, int n, double eta2,
 
 // Steps 1-2 at one k-point, one wavefront: H(k), its eigenvalues (S.E) and
 // eigenvectors (S.U).  Returns false on QL non-convergence or non-finite values.
+//
+// v_x is built from the same loads of the pencil partial sums as H and parked
+// in S.U until U takes its place, then moved to S.P; on return vx_in_p says
+// whether S.P holds it (not after the QL path, which needs S.U for Z).
 template <int NP>
 __device__ bool wave_eigen(WaveLds<NP>& S, const ModelDev& md, const double2* __restrict__ T0,
-                           const int* __restrict__ r0, int i0, int max_iter) {
+                           const int* __restrict__ r0, int i0, int max_iter, bool& vx_in_p) {
     constexpr int LD = WaveLds<NP>::LD;
     const int lane = threadIdx.x & 63;
     const int n = md.n;
@@ -722,39 +726,48 @@ __device__ bool wave_eigen(WaveLds<NP>& S, const ModelDev& md, const double2* __
     if (lane < md.nR0) S.ph[lane] = unit_phase((long long)i0 * r0[lane], md.N0);
     __syncthreads();
     {
-        // upper triangle from the pencil partial sums (all loads of one rho in
-        // flight together), mirrored so that H is exactly Hermitian
+        // H (upper triangle, mirrored so that it is exactly Hermitian) and v_x
+        // from one pass over the pencil partial sums, all loads of one rho in flight
         constexpr int PER = NP * NP / 64;
-        double2 acc[PER];
+        double2 acc[PER], accx[PER];
         int off[PER];
         bool valid[PER];
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int e = lane + 64 * q;
             const int i = e / NP, j = e % NP;
-            valid[q] = (i <= j) && (j < n);
+            valid[q] = (i < n) && (j < n);
             off[q] = i * n + j;
             acc[q] = c_make(0.0, 0.0);
+            accx[q] = c_make(0.0, 0.0);
         }
         for (int rho = 0; rho < md.nR0; ++rho) {
             const double2 ph = S.ph[rho];
+            const double2 cf = c_scale((double)r0[rho], c_i(ph));
             const double2* Tr = T0 + (long long)rho * nn;
 #pragma unroll
-            for (int q = 0; q < PER; ++q)
-                if (valid[q]) acc[q] = c_fma(Tr[off[q]], ph, acc[q]);
+            for (int q = 0; q < PER; ++q) {
+                if (valid[q]) {
+                    const double2 tv = Tr[off[q]];
+                    acc[q] = c_fma(tv, ph, acc[q]);
+                    accx[q] = c_fma(cf, tv, accx[q]);
+                }
+            }
         }
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-            if (valid[q]) {
-                const int e = lane + 64 * q;
-                const int i = e / NP, j = e % NP;
+            const int e = lane + 64 * q;
+            const int i = e / NP, j = e % NP;
+            if (valid[q] && i <= j) {
                 double2 h = acc[q];
                 if (i == j) h.y = 0.0;
                 S.P[i * LD + j] = h;
                 S.P[j * LD + i] = c_conj(h);
             }
+            S.U[i * LD + j] = valid[q] ? accx[q] : c_make(0.0, 0.0);
         }
     }
+    vx_in_p = true;
     __syncthreads();
     double d_lane, e_lane;
     wave_tridiag<NP>(S, n, d_lane, e_lane);
@@ -788,6 +801,7 @@ __device__ bool wave_eigen(WaveLds<NP>& S, const ModelDev& md, const double2* __
         }
     } else {
         // a cluster: implicit QL with accumulated rotations (Z in S.U, lane = row)
+        vx_in_p = false;
         for (int e = lane; e < n * n; e += 64) {
             const int i = e / n, j = e - (e / n) * n;
             S.U[i * LD + j] = c_make(i == j ? 1.0 : 0.0, 0.0);
@@ -806,10 +820,23 @@ __device__ bool wave_eigen(WaveLds<NP>& S, const ModelDev& md, const double2* __
     if (__ballot(!ok) != 0ull) ok = false;
     wave_backtransform<NP>(S, n, u);
     __syncthreads();
+    if (vx_in_p) {
+        // the reflectors are spent: v_x moves from S.U to S.P
+        constexpr int PER = NP * NP / 64;
 #pragma unroll
-    for (int jj = 0; jj < HW; ++jj) {
-        const int r = c0 + jj;
-        if (c < n && r < n) S.U[r * LD + c] = u[jj];
+        for (int q = 0; q < PER; ++q) {
+            const int e = lane + 64 * q;
+            const int idx = (e / NP) * LD + (e % NP);
+            S.P[idx] = S.U[idx];
+        }
+        __syncthreads();
+    }
+    if (c < NP) {
+#pragma unroll
+        for (int jj = 0; jj < HW; ++jj) {
+            const int r = c0 + jj;
+            S.U[r * LD + c] = (c < n && r < n) ? u[jj] : c_make(0.0, 0.0);
+        }
     }
     __syncthreads();
     return ok;
@@ -844,14 +871,17 @@ __global__ __launch_bounds__(64) void k_forward_wave(FwdLaunch a) {
         const double* ef = a.e_fermi + md.f_off;
         double* part = a.partial + (long long)it.slot * a.nF;
         for (int kk = 0; kk < it.count; ++kk) {
-            const bool ok = wave_eigen<NP>(S, md, T0, r0, it.i0 + kk, max_iter);
+            bool vx_in_p;
+            const bool ok = wave_eigen<NP>(S, md, T0, r0, it.i0 + kk, max_iter, vx_in_p);
             if (!ok && lane == 0) atomicOr(a.status, kStatNoConv);
             if constexpr (NT >= 1) {
                 // A = U^+ v_x U, B = U^+ v_y U on the matrix cores
                 double2 u[NT][4][NT];
                 wave_load_uops<NP>(S, u);
-                wave_stage_velocity<NP>(S, n, md.nR0, T0, r0, true);
-                __syncthreads();
+                if (!vx_in_p) {
+                    wave_stage_velocity<NP>(S, n, md.nR0, T0, r0, true);
+                    __syncthreads();
+                }
                 v4d ar[NT][NT], ai[NT][NT], br[NT][NT], bi[NT][NT];
                 wave_rotate_mfma<NP>(S, u, ar, ai);
                 __syncthreads();
@@ -1070,14 +1100,17 @@ __global__ __launch_bounds__(64) void k_adjoint_wave(WgLaunch a) {
         const double invN = 1.0 / (double)md.Nk;
         for (int kk = 0; kk < it.count; ++kk) {
             // ---- recompute: E, U, A = U^+ v_x U, B = U^+ v_y U
-            const bool ok = wave_eigen<NP>(S, md, T0, r0, it.i0 + kk, max_iter);
+            bool vx_in_p;
+            const bool ok = wave_eigen<NP>(S, md, T0, r0, it.i0 + kk, max_iter, vx_in_p);
             if (!ok && lane == 0) atomicOr(a.status, kStatNoConv);
             v4d ar[NT][NT], ai[NT][NT], br[NT][NT], bi[NT][NT];
             {
                 double2 u[NT][4][NT];
                 wave_load_uops<NP>(S, u);
-                wave_stage_velocity<NP>(S, n, md.nR0, T0, r0, true);
-                __syncthreads();
+                if (!vx_in_p) {
+                    wave_stage_velocity<NP>(S, n, md.nR0, T0, r0, true);
+                    __syncthreads();
+                }
                 wave_rotate_mfma<NP>(S, u, ar, ai);
                 __syncthreads();
                 wave_stage_velocity<NP>(S, n, md.nR0, T1, r0, false);
