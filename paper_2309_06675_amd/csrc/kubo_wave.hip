@@ -116,9 +116,11 @@ struct WaveLds {
 };
 
 // Reduce the Hermitian matrix in S.P (n x n) to real tridiagonal form.
-// The matrix lives in registers: lane 2i + h holds row i, columns
-// [h NP/2, (h+1) NP/2).  Each step broadcasts the reflector v and the vector
-// w through LDS and applies A <- A - v w^+ - w v^+ in registers.
+// The matrix lives in registers: lane 2i + h holds row i, columns 2 jj + h
+// (jj < NP/2).  Each step broadcasts the reflector v and the vector w through
+// LDS and applies A <- A - v w^+ - w v^+ in registers; groups of four slots
+// whose eight columns are all reduced already are skipped (a wave-uniform
+// test), which saves about 40% of the work over the whole reduction.
 // On return lane i holds d_i and e_i (e_{n-1} = 0); the Householder vector of
 // step k is stored in S.P column k below the diagonal (row k+1 holds 1) and
 // its scalar in S.tau[k]; H = Q T Q^+ with Q = H_0 H_1 ... H_{n-2},
@@ -128,16 +130,21 @@ __device__ void wave_tridiag(WaveLds<NP>& S, int n, double& d_lane, double& e_la
     constexpr int LD = WaveLds<NP>::LD;
     constexpr int HW = NP / 2;
     const int lane = threadIdx.x & 63;
-    const int i = lane >> 1, h = lane & 1, c0 = h * HW;
+    const int i = lane >> 1, h = lane & 1;
     const bool row_ok = i < n;
+    // reciprocal: hardware estimate and one Newton step
+    auto rcp = [](double x) {
+        const double r = __builtin_amdgcn_rcp(x);
+        return fma(r, fma(-x, r, 1.0), r);
+    };
     double2 a[HW];
 #pragma unroll
     for (int jj = 0; jj < HW; ++jj)
-        a[jj] = (row_ok && c0 + jj < n) ? S.P[i * LD + c0 + jj] : c_make(0.0, 0.0);
+        a[jj] = (row_ok && 2 * jj + h < n) ? S.P[i * LD + 2 * jj + h] : c_make(0.0, 0.0);
     d_lane = 0.0;
     e_lane = 0.0;
     for (int k = 0; k < n - 1; ++k) {
-        const int hk = k / HW, jk = k - hk * HW;  // half and slot holding column k
+        const int hk = k & 1, jk = k >> 1;  // lane half and slot holding column k
         double2 xk = c_make(0.0, 0.0);
 #pragma unroll
         for (int jj = 0; jj < HW; ++jj)
@@ -158,10 +165,11 @@ __device__ void wave_tridiag(WaveLds<NP>& S, int n, double& d_lane, double& e_la
         } else {
             const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn2);
             beta = -copysign(nrm, alpha.x);
-            tau = c_make((beta - alpha.x) / beta, -alpha.y / beta);
+            const double ib = rcp(beta);
+            tau = c_make((beta - alpha.x) * ib, -alpha.y * ib);
             // 1 / (alpha - beta)
             const double ar = alpha.x - beta, ai = alpha.y;
-            const double den = 1.0 / (ar * ar + ai * ai);
+            const double den = rcp(ar * ar + ai * ai);
             scal = c_make(ar * den, -ai * den);
         }
         double2 v = c_make(0.0, 0.0);
@@ -183,11 +191,18 @@ __device__ void wave_tridiag(WaveLds<NP>& S, int n, double& d_lane, double& e_la
         if (tau.x == 0.0 && tau.y == 0.0) continue;
         // p = A v (row i), the two halves combined within the lane pair
         double2 vc[HW];
-#pragma unroll
-        for (int jj = 0; jj < HW; ++jj) vc[jj] = S.vv[c0 + jj];
         double2 p = c_make(0.0, 0.0);
 #pragma unroll
-        for (int jj = 0; jj < HW; ++jj) p = c_fma(a[jj], vc[jj], p);
+        for (int gq = 0; gq < HW / 4; ++gq) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) vc[4 * gq + t] = c_make(0.0, 0.0);
+            if (8 * gq + 7 > k) {  // some column of this group of four slots is still live
+#pragma unroll
+                for (int t = 0; t < 4; ++t) vc[4 * gq + t] = S.vv[2 * (4 * gq + t) + h];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) p = c_fma(a[4 * gq + t], vc[4 * gq + t], p);
+            }
+        }
         p = c_make(p.x + dpp_xor1(p.x), p.y + dpp_xor1(p.y));
         const double mu = wave_sum(h == 0 ? (v.x * p.x + v.y * p.y) : 0.0);  // v^+ p (real)
         const double t2 = 0.5 * (tau.x * tau.x + tau.y * tau.y) * mu;
@@ -197,14 +212,22 @@ __device__ void wave_tridiag(WaveLds<NP>& S, int n, double& d_lane, double& e_la
         __syncthreads();
         // A <- A - v w^+ - w v^+ (v_c = w_c = 0 for c <= k keeps the stored reflectors)
 #pragma unroll
-        for (int jj = 0; jj < HW; ++jj) {
-            const double2 wc = S.wv[c0 + jj];
-            a[jj] = c_sub(a[jj], c_add(c_mulc(v, wc), c_mulc(w, vc[jj])));
+        for (int gq = 0; gq < HW / 4; ++gq) {
+            if (8 * gq + 7 > k) {
+                double2 wc[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) wc[t] = S.wv[2 * (4 * gq + t) + h];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int jj = 4 * gq + t;
+                    a[jj] = c_sub(a[jj], c_add(c_mulc(v, wc[t]), c_mulc(w, vc[jj])));
+                }
+            }
         }
         __syncthreads();
     }
     {
-        const int hl = (n - 1) / HW, jl = (n - 1) - hl * HW;
+        const int hl = (n - 1) & 1, jl = (n - 1) >> 1;
         double2 last = c_make(0.0, 0.0);
 #pragma unroll
         for (int jj = 0; jj < HW; ++jj)
@@ -218,7 +241,7 @@ __device__ void wave_tridiag(WaveLds<NP>& S, int n, double& d_lane, double& e_la
     // reflectors back to LDS for the back-transformation
 #pragma unroll
     for (int jj = 0; jj < HW; ++jj)
-        if (row_ok && c0 + jj < i) S.P[i * LD + c0 + jj] = a[jj];
+        if (row_ok && 2 * jj + h < i) S.P[i * LD + 2 * jj + h] = a[jj];
     __syncthreads();
 }
 
@@ -390,8 +413,8 @@ __device__ double wave_bisect(const WaveLds<NP>& S, int n, double glo, double gh
 // Eigenvector of the tridiagonal matrix for an isolated eigenvalue lam by the
 // twisted factorisation of T - lam I: forward pivots dp, backward pivots dm,
 // twist index r = argmin |dp_r + dm_r - (d_r - lam)|, then z_r = 1 and the two
-// one-sided recurrences.  The lane keeps half `h` of the normalised vector:
-// u[jj] = z[h NP/2 + jj].
+// one-sided recurrences.  The lane keeps the rows of parity h of the
+// normalised vector: u[jj] = z[2 jj + h].
 template <int NP>
 __device__ void wave_twisted(const WaveLds<NP>& S, int n, double& lam, double pivmin, int h,
                              double2 (&u)[NP / 2]) {
@@ -463,36 +486,47 @@ __device__ void wave_twisted(const WaveLds<NP>& S, int n, double& lam, double pi
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
         const double zi = (i < r) ? dp[i] : ((i == r) ? 1.0 : dm[i]);
-        if (i / (NP / 2) == h) u[i % (NP / 2)] = c_make(zi * inv, 0.0);
+        if ((i & 1) == h) u[i >> 1] = c_make(zi * inv, 0.0);
     }
 }
 
-// U <- H_0 H_1 ... H_{n-2} Z in registers: lane 2c + h holds rows
-// [h NP/2, (h+1) NP/2) of column c in u[] (Z on entry); the reflectors are
-// read from S.P (column k below the diagonal) as broadcasts.
+// U <- H_0 H_1 ... H_{n-2} Z in registers: lane 2c + h holds rows 2 jj + h
+// of column c in u[jj] (Z on entry); the reflectors are read from S.P
+// (column k below the diagonal) as broadcasts, and groups of four slots whose
+// eight rows are all above the reflector are skipped.
 template <int NP>
 __device__ void wave_backtransform(const WaveLds<NP>& S, int n, double2 (&u)[NP / 2]) {
     constexpr int LD = WaveLds<NP>::LD;
     constexpr int HW = NP / 2;
-    const int lane = threadIdx.x & 63;
-    const int c0 = (lane & 1) * HW;
+    const int h = threadIdx.x & 1;
     for (int k = n - 2; k >= 0; --k) {
         const double2 tau = S.tau[k];
         if (tau.x == 0.0 && tau.y == 0.0) continue;
         double2 vr[HW];
+        double2 y = c_make(0.0, 0.0);  // v^+ u over this lane's rows of the column
 #pragma unroll
-        for (int jj = 0; jj < HW; ++jj) {
-            const int r = c0 + jj;
-            const double2 x = S.P[r * LD + k];
-            vr[jj] = (r > k && r < n) ? x : c_make(0.0, 0.0);
+        for (int gq = 0; gq < HW / 4; ++gq) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) vr[4 * gq + t] = c_make(0.0, 0.0);
+            if (8 * gq + 7 > k) {  // some row of this group of four slots is below the reflector's top
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int r = 2 * (4 * gq + t) + h;
+                    const double2 x = S.P[r * LD + k];
+                    vr[4 * gq + t] = (r > k && r < n) ? x : c_make(0.0, 0.0);
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t) y = c_fmac(vr[4 * gq + t], u[4 * gq + t], y);
+            }
         }
-        double2 y = c_make(0.0, 0.0);  // v^+ u over this half of the column
-#pragma unroll
-        for (int jj = 0; jj < HW; ++jj) y = c_fmac(vr[jj], u[jj], y);
         y = c_make(y.x + dpp_xor1(y.x), y.y + dpp_xor1(y.y));
         const double2 ty = c_mul(tau, y);
 #pragma unroll
-        for (int jj = 0; jj < HW; ++jj) u[jj] = c_sub(u[jj], c_mul(vr[jj], ty));
+        for (int gq = 0; gq < HW / 4; ++gq)
+            if (8 * gq + 7 > k) {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) u[4 * gq + t] = c_sub(u[4 * gq + t], c_mul(vr[4 * gq + t], ty));
+            }
     }
 }
 
@@ -783,7 +817,7 @@ __device__ bool wave_eigen(WaveLds<NP>& S, const ModelDev& md, const double2* __
     bool ok = true;
     const double lam2 = wave_bisect<NP>(S, n, glo, ghi, pivmin);  // lanes 2j, 2j+1: eigenvalue j
     constexpr int HW = NP / 2;
-    const int c = lane >> 1, h = lane & 1, c0 = h * HW;
+    const int c = lane >> 1, h = lane & 1;
     const double lnext = __shfl_down(lam2, 2, 64);
     const double span = fmax(fabs(glo), fabs(ghi));
     const bool close = (c < n - 1) && (lnext - lam2 < 1e-3 * span);
@@ -813,7 +847,7 @@ __device__ bool wave_eigen(WaveLds<NP>& S, const ModelDev& md, const double2* __
         __syncthreads();
 #pragma unroll
         for (int jj = 0; jj < HW; ++jj) {
-            const int r = c0 + jj;
+            const int r = 2 * jj + h;
             u[jj] = (c < n && r < n) ? c_make(S.U[r * LD + c].x, 0.0) : c_make(0.0, 0.0);
         }
     }
@@ -834,7 +868,7 @@ __device__ bool wave_eigen(WaveLds<NP>& S, const ModelDev& md, const double2* __
     if (c < NP) {
 #pragma unroll
         for (int jj = 0; jj < HW; ++jj) {
-            const int r = c0 + jj;
+            const int r = 2 * jj + h;
             S.U[r * LD + c] = (c < n && r < n) ? u[jj] : c_make(0.0, 0.0);
         }
     }
