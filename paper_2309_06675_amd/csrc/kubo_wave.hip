@@ -342,13 +342,17 @@ __device__ bool wave_ql(WaveLds<NP>& S, int n, double& d_lane, double& e_lane, i
 
 // Eigenvalues of the real symmetric tridiagonal (d, e) in S.de2 by Sturm-count
 // multisection.  Lanes 2j and 2j+1 search eigenvalue j (ascending): each step
-// they count at six interior points of [lo, hi] (three interleaved Sturm
-// sequences per lane, which hides the latency of the recurrence) and keep the
-// seventh that holds eigenvalue j.  A fixed number of steps shrinks the
-// Gershgorin interval below 4 eps max|lambda|.  Returns lambda_j in both lanes.
+// they count at 2 NS interior points of [lo, hi] (NS interleaved Sturm
+// sequences per lane) and keep the sub-interval that holds eigenvalue j.
+// With the tridiagonal matrix in registers the recurrence is issue bound, so
+// the total count of sequence steps (NS times the number of steps) decides:
+// NS = 1 (trisection) measured fastest, ahead of 2 and 3.
+// A fixed number of steps shrinks the Gershgorin interval below 4 eps max|lambda|.
+// Returns lambda_j in both lanes.
 template <int NP>
 __device__ double wave_bisect(const WaveLds<NP>& S, int n, double glo, double ghi, double pivmin) {
-    constexpr int NS = 3;  // points per lane
+    constexpr int NS = 1;  // points per lane
+    constexpr double inv_sections = 1.0 / (2 * NS + 1);
     const int lane = threadIdx.x & 63;
     const int j = lane >> 1;
     const int half = lane & 1;
@@ -364,9 +368,9 @@ __device__ double wave_bisect(const WaveLds<NP>& S, int n, double glo, double gh
     const double scale = fmax(fabs(glo), fabs(ghi));
     const double tol = 4.0 * 2.220446049250313e-16 * scale + 1e-300;
     int steps = 0;
-    for (double w = ghi - glo; w > tol && steps < 60; w *= (1.0 / 7.0)) ++steps;
+    for (double w = ghi - glo; w > tol && steps < 60; w *= inv_sections) ++steps;
     for (int it = 0; it < steps; ++it) {
-        const double step = (hi - lo) * (1.0 / 7.0);
+        const double step = (hi - lo) * inv_sections;
         double x[NS], q[NS];
         int cnt[NS];
 #pragma unroll
@@ -389,7 +393,7 @@ __device__ double wave_bisect(const WaveLds<NP>& S, int n, double glo, double gh
                 q[t] = qi;
             }
         }
-        // counts at the six points, ascending: this lane's and its partner's
+        // counts at the 2 NS points, ascending: this lane's and its partner's
         int c[2 * NS];
 #pragma unroll
         for (int t = 0; t < NS; ++t) {
