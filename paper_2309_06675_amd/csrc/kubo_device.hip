@@ -271,11 +271,92 @@ hipError_t launch_hermproj(const Tables& tb, int n_models, long long total, cons
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// k_pacc: pencil sums of the one-wavefront adjoint's per-k matrices, one
+// workgroup per (k-block, 256 matrix elements).  For each R_x value rho:
+//   PH_rho = sum_k e^{-i k0 rho} (Hbar - i rho vbar_x),  PY_rho = sum_k e^{-i k0 rho} vbar_y,
+// summed over the block's k-points in order.  The phases of up to 32
+// k-points at a time sit in LDS.
+// ---------------------------------------------------------------------------
+constexpr int kPaccThreads = 256;
+constexpr int kPaccTile = 32;
+
+__global__ __launch_bounds__(kPaccThreads) void k_pacc(Tables tb, int begin, const double2* __restrict__ xbuf,
+                                                        double2* __restrict__ pbuf, unsigned* status) {
+    __shared__ double2 ph[kPaccTile][kMaxR0];
+    const BlockItem it = tb.blocks[begin + blockIdx.x];
+    const ModelDev md = tb.models[it.model];
+    const long long nn = (long long)md.n * md.n;
+    if ((long long)blockIdx.y * kPaccThreads >= nn) return;  // whole workgroup past this matrix
+    const long long e = (long long)blockIdx.y * kPaccThreads + threadIdx.x;
+    const bool act = e < nn;
+    const int nR0 = md.nR0;
+    const int* r0 = tb.r0val + md.r0_first;
+    const double2* X = xbuf + it.xbuf_off;
+    double2 accH[kMaxR0], accY[kMaxR0];
+#pragma unroll
+    for (int rho = 0; rho < kMaxR0; ++rho) {
+        accH[rho] = c_make(0.0, 0.0);
+        accY[rho] = c_make(0.0, 0.0);
+    }
+    for (int k0 = 0; k0 < it.count; k0 += kPaccTile) {
+        const int kc = (it.count - k0 < kPaccTile) ? it.count - k0 : kPaccTile;
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < kc * nR0; idx += kPaccThreads) {
+            const int kk = idx / nR0, rho = idx - kk * nR0;
+            ph[kk][rho] = c_conj(unit_phase((long long)(it.i0 + k0 + kk) * r0[rho], md.N0));
+        }
+        __syncthreads();
+        if (act) {
+            for (int kk = 0; kk < kc; ++kk) {
+                const double2* Xk = X + (long long)(k0 + kk) * 3 * nn;
+                const double2 h = Xk[e], vx = Xk[nn + e], vy = Xk[2 * nn + e];
+                const bool first = (k0 + kk == 0);
+#pragma unroll
+                for (int rho = 0; rho < kMaxR0; ++rho) {
+                    if (rho < nR0) {
+                        const double2 pc = ph[kk][rho];
+                        const double rr = (double)r0[rho];
+                        const double2 w = c_make(h.x + rr * vx.y, h.y - rr * vx.x);
+                        const double2 h1 = c_mul(pc, w);
+                        const double2 y1 = c_mul(pc, vy);
+                        accH[rho] = first ? h1 : c_add(accH[rho], h1);
+                        accY[rho] = first ? y1 : c_add(accY[rho], y1);
+                    }
+                }
+            }
+        }
+    }
+    if (act) {
+        double2* PH = pbuf + it.pbuf_off;
+        double2* PY = PH + (long long)nR0 * nn;
+        bool bad = false;
+#pragma unroll
+        for (int rho = 0; rho < kMaxR0; ++rho) {
+            if (rho < nR0) {
+                PH[rho * nn + e] = accH[rho];
+                PY[rho * nn + e] = accY[rho];
+                bad |= !isfinite(accH[rho].x + accH[rho].y + accY[rho].x + accY[rho].y);
+            }
+        }
+        if (bad) atomicOr(status, kStatNonFinite);
+    }
+}
+
 hipError_t launch_pencil(const Tables& tb, int item_begin, int item_count, const double* tp,
                          double* tbuf, hipStream_t s) {
     if (item_count <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_pencil, dim3(item_count), dim3(kPencilThreads), 0, s, tb, item_begin,
                        reinterpret_cast<const double2*>(tp), reinterpret_cast<double2*>(tbuf));
+    return hipGetLastError();
+}
+
+hipError_t launch_pacc(const Tables& tb, int begin, int count, long long max_nn, const double* xbuf,
+                       double* pbuf, unsigned* status, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    const unsigned ty = (unsigned)((max_nn + kPaccThreads - 1) / kPaccThreads);
+    hipLaunchKernelGGL(k_pacc, dim3(count, ty), dim3(kPaccThreads), 0, s, tb, begin,
+                       reinterpret_cast<const double2*>(xbuf), reinterpret_cast<double2*>(pbuf), status);
     return hipGetLastError();
 }
 

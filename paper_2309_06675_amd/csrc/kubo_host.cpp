@@ -49,7 +49,7 @@ struct Chunk {
     int grange_begin = 0, grange_count = 0;
     ClassRange cls[kNumClasses];
     long long cls_kpts[kNumClasses] = {0};
-    size_t tbytes = 0, pbytes = 0;
+    size_t tbytes = 0, pbytes = 0, xbytes = 0;
 };
 
 struct GraphKey {
@@ -93,13 +93,14 @@ struct kubo_plan_s {
         std::vector<BlockItem> blocks;
         std::vector<GaccRange> granges;
         std::vector<Chunk> chunks;
-        size_t max_t = 0, max_p = 0;
+        size_t max_t = 0, max_p = 0, max_x = 0;
         size_t tab_pencils = 0, tab_blocks = 0, tab_granges = 0;
     } fwd, bwd;
     int n_slots = 0;
     long long t_elems = 0;  // complex elements of t (all models)
     // workspace layout
-    size_t off_tables = 0, off_tp = 0, off_tbuf = 0, off_pbuf = 0, off_partial = 0, total = 0;
+    size_t off_tables = 0, off_tp = 0, off_tbuf = 0, off_pbuf = 0, off_xbuf = 0, off_partial = 0,
+           total = 0;
     size_t off_scratch = 0;
     long long slot_elems = 0;
     int wg_groups = 512;
@@ -163,6 +164,7 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
         std::vector<BlockItem> blocks;   // forward k-blocks (the tile's k_block)
         std::vector<BlockItem> bblocks;  // backward k-blocks: longer, so fewer pencil partials
         size_t tbytes, pbytes;
+        size_t xbytes;  // backward, one-wavefront classes: the per-k adjoint matrices
         int cls;
     };
     std::vector<PB> all;
@@ -257,6 +259,7 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
                     pb.bblocks.push_back(bi);
                 }
                 pb.pbytes = mat_bytes * pb.bblocks.size();
+                pb.xbytes = kClasses[cls].wave ? (size_t)3 * nn * 16 * (size_t)(a1 - a0) : 0;
                 all.push_back(std::move(pb));
             }
         }
@@ -311,6 +314,7 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
             cur.grange_count = (int)cs.granges.size() - cur.grange_begin;
             cs.max_t = std::max(cs.max_t, cur.tbytes);
             cs.max_p = std::max(cs.max_p, cur.pbytes);
+            cs.max_x = std::max(cs.max_x, cur.xbytes);
             cs.chunks.push_back(cur);
             cur = Chunk();
             cur.pencil_begin = (int)cs.pencils.size();
@@ -319,22 +323,33 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
         for (const auto& pb0 : all) {
             PB pb = pb0;
             if (cur.pencil_count > 0 &&
-                (cur.tbytes + pb.tbytes > cap || (with_p && cur.pbytes + pb.pbytes > 4 * cap)))
+                (cur.tbytes + pb.tbytes > cap ||
+                 (with_p && cur.pbytes + cur.xbytes + pb.pbytes + pb.xbytes > 4 * cap)))
                 flush();
             PencilItem pi = pb.pi;
             pi.tbuf_off = (long long)(cur.tbytes / 16);
             long long poff = (long long)(cur.pbytes / 16);
+            long long xoff = (long long)(cur.xbytes / 16);
             const long long mat = (long long)(pb.tbytes / 16);
+            const long long nn = (long long)models[pi.model].n_orb * models[pi.model].n_orb;
             for (auto& b : (with_p ? pb.bblocks : pb.blocks)) {
                 b.tbuf_off = pi.tbuf_off;
                 b.pbuf_off = with_p ? poff : 0;
-                if (with_p) poff += mat;
+                b.xbuf_off = -1;
+                if (with_p) {
+                    poff += mat;
+                    if (kClasses[pb.cls].wave) {
+                        b.xbuf_off = xoff;
+                        xoff += 3 * nn * b.count;
+                    }
+                }
                 cls_blocks[pb.cls].push_back(b);
             }
             cs.pencils.push_back(pi);
             cur.pencil_count++;
             cur.tbytes += pb.tbytes;
             cur.pbytes += pb.pbytes;
+            if (with_p) cur.xbytes += pb.xbytes;
         }
         flush();
     };
@@ -367,6 +382,8 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
     off = align_up(off + max_t);
     P->off_pbuf = off;
     if (!(P->flags & KUBO_F_FORWARD_ONLY)) off = align_up(off + max_p);
+    P->off_xbuf = off;
+    if (!(P->flags & KUBO_F_FORWARD_ONLY)) off = align_up(off + P->bwd.max_x);
     P->off_partial = off;
     off = align_up(off + (size_t)P->n_slots * nF * 8);
     {
@@ -545,6 +562,7 @@ kubo_status enqueue_backward(kubo_plan_s* P, const double* t, const double* ef, 
     double* tp = reinterpret_cast<double*>(ws + P->off_tp);
     double* tbuf = reinterpret_cast<double*>(ws + P->off_tbuf);
     double* pbuf = reinterpret_cast<double*>(ws + P->off_pbuf);
+    double* xbuf = reinterpret_cast<double*>(ws + P->off_xbuf);
     double* scratch = reinterpret_cast<double*>(ws + P->off_scratch);
     const int max_iter = (P->flags & KUBO_F_DEBUG_SWEEPCAP) ? 1 : kMaxSweeps;
     HIP_TRY(launch_clear(status, s));
@@ -563,6 +581,7 @@ kubo_status enqueue_backward(kubo_plan_s* P, const double* t, const double* ef, 
             L.partial = nullptr;
             L.status = status;
             L.scratch = scratch;
+            L.xbuf = xbuf;
             L.slot_elems = P->slot_elems;
             L.eta = eta;
             L.kT = kT;
@@ -579,6 +598,8 @@ kubo_status enqueue_backward(kubo_plan_s* P, const double* t, const double* ef, 
                 HIP_TRY(launch_adjoint_wg(L, s));
             }
             ts.finish();
+            if (kClasses[k].wave)
+                HIP_TRY(launch_pacc(tb, c.cls[k].begin, c.cls[k].count, P->max_nn, xbuf, pbuf, status, s));
         }
         HIP_TRY(launch_gacc(tb, tb.granges, c.grange_begin, c.grange_count, P->max_nR, P->max_nn,
                             pbuf, grad, s));

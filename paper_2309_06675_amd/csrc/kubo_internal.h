@@ -43,7 +43,11 @@ struct BlockItem {
     int i1, i2, pad0, pad1;
     long long tbuf_off;  // its pencil's T matrices (chunk-relative)
     long long pbuf_off;  // adjoint: its pencil-sum matrices (chunk-relative)
+    long long xbuf_off;  // adjoint, one-wavefront classes: its k-points' Hbar, vbar_x,
+                         // vbar_y (chunk-relative; -1 for the workgroup class)
 };
+
+constexpr int kMaxR0 = 16;  // distinct R_x values per model
 
 // A run of consecutive k-blocks of one model (the adjoint's transposed Bloch sum).
 struct GaccRange {

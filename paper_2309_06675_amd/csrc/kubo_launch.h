@@ -30,6 +30,7 @@ struct WgLaunch {
     double* partial;
     unsigned* status;
     double* scratch;       // max_groups slots of slot_elems complex elements
+    double* xbuf;          // per-k adjoint matrices of the one-wavefront classes
     long long slot_elems;
     double eta, kT;
     int nF;
@@ -51,6 +52,10 @@ hipError_t launch_hermproj(const Tables& tb, int n_models, long long total, cons
 hipError_t launch_pencil(const Tables& tb, int item_begin, int item_count, const double* tp,
                          double* tbuf, hipStream_t s);
 hipError_t launch_forward_wave(const FwdLaunch& L, hipStream_t s);
+// pencil sums of the adjoint matrices of blocks [begin, begin + count):
+// PH_rho = sum_k e^{-i k0 rho}(Hbar - i rho vbar_x), PY_rho = sum_k e^{-i k0 rho} vbar_y
+hipError_t launch_pacc(const Tables& tb, int begin, int count, long long max_nn, const double* xbuf,
+                       double* pbuf, unsigned* status, hipStream_t s);
 hipError_t launch_gacc(const Tables& tb, const GaccRange* ranges, int range_begin, int range_count,
                        int max_nR, long long max_nn, const double* pbuf, double* grad,
                        hipStream_t s);

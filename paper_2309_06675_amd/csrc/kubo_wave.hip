@@ -1007,9 +1007,10 @@ hipError_t launch_forward_wave(const FwdLaunch& L, hipStream_t s) {
 //           pairs closer than delta, the divided-difference limit
 //           (i/N) sum_p dK(x, E_p)/dx at x = (E_m + E_q)/2 (B_mp A_pq - A_mp B_pq)
 //   Hbar  = U Hbar' U^+,  vbar_x = U Abar U^+,  vbar_y = U Bbar U^+
-// and the block's pencil partials PH_rho += e^{-i k0 rho}(Hbar - i rho vbar_x),
-// PY_rho += e^{-i k0 rho} vbar_y.  Every matrix is held in the accumulator
-// layout: element q of lane l's tile (ti, tj) is M[16 ti + g + 4 q][16 tj + c].
+// stored per k-point (Hbar, vbar_x, vbar_y); a separate pass forms the
+// block's pencil partials from them.  Every matrix is held in the
+// accumulator layout: element q of lane l's tile (ti, tj) is
+// M[16 ti + g + 4 q][16 tj + c].
 // ---------------------------------------------------------------------------
 
 // f(x) and f'(x) summed against sbar: one exponential per Fermi level
@@ -1118,7 +1119,7 @@ __global__ __launch_bounds__(64) void k_adjoint_wave(WgLaunch a) {
     const double delta = 1e-5 * scl;
     const int max_iter = a.max_iter >= kMaxSweeps ? 30 : 1;
     const double2* tbuf = reinterpret_cast<const double2*>(a.tbuf);
-    double2* pbuf = reinterpret_cast<double2*>(a.pbuf);
+    double2* xb = reinterpret_cast<double2*>(a.xbuf);
     const v4d zero = {0.0, 0.0, 0.0, 0.0};
     for (int e = lane; e < NP * LD; e += 64) S.U[e] = c_make(0.0, 0.0);
     __syncthreads();
@@ -1130,8 +1131,6 @@ __global__ __launch_bounds__(64) void k_adjoint_wave(WgLaunch a) {
         const long long nn = (long long)n * n;
         const double2* T0 = tbuf + it.tbuf_off;
         const double2* T1 = T0 + (long long)md.nR0 * nn;
-        double2* PH = pbuf + it.pbuf_off;
-        double2* PY = PH + (long long)md.nR0 * nn;
         const int* r0 = a.tb.r0val + md.r0_first;
         const double* ef = a.e_fermi + md.f_off;
         const double* sb = a.sbar + md.f_off;
@@ -1349,7 +1348,9 @@ __global__ __launch_bounds__(64) void k_adjoint_wave(WgLaunch a) {
                         S.U[(16 * ti + g + 4 * q) * LD + 16 * tj + c16] =
                             c_make(kv * ai[ti][tj][q], -kv * ar[ti][tj][q]);
                     }
-            // ---- vbar_x = U Abar U^+ (parked in S.P), Hbar = U Hbar' U^+ -> PH
+            // ---- vbar_x = U Abar U^+, Hbar = U Hbar' U^+, vbar_y = U Bbar U^+, stored for
+            // this k-point (the pencil sums over the block are taken by a separate pass)
+            double2* Xk = xb + it.xbuf_off + (long long)kk * 3 * nn;
             {
                 v4d vr_[NT][NT], vi_[NT][NT];
                 wave_sandwich<NP>(xr, xi, ua, vr_, vi_);
@@ -1358,37 +1359,24 @@ __global__ __launch_bounds__(64) void k_adjoint_wave(WgLaunch a) {
 #pragma unroll
                     for (int tj = 0; tj < NT; ++tj)
 #pragma unroll
-                        for (int q = 0; q < 4; ++q)
-                            S.P[(16 * ti + g + 4 * q) * LD + 16 * tj + c16] = c_make(vr_[ti][tj][q], vi_[ti][tj][q]);
+                        for (int q = 0; q < 4; ++q) {
+                            const int m = 16 * ti + g + 4 * q, c = 16 * tj + c16;
+                            if (m < n && c < n) Xk[nn + (long long)m * n + c] = c_make(vr_[ti][tj][q], vi_[ti][tj][q]);
+                        }
             }
-            bool bad = false;
             {
                 v4d hbr[NT][NT], hbi[NT][NT];
                 wave_sandwich<NP>(hr, hi, ua, hbr, hbi);
-                for (int rho = 0; rho < md.nR0; ++rho) {
-                    const double2 pc = c_conj(S.ph[rho]);
-                    const double rr = (double)r0[rho];
-                    double2* ph_ = PH + (long long)rho * nn;
 #pragma unroll
-                    for (int ti = 0; ti < NT; ++ti)
+                for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
-                        for (int tj = 0; tj < NT; ++tj)
+                    for (int tj = 0; tj < NT; ++tj)
 #pragma unroll
-                            for (int q = 0; q < 4; ++q) {
-                                const int m = 16 * ti + g + 4 * q, c = 16 * tj + c16;
-                                if (m < n && c < n) {
-                                    // Hbar - i rho vbar_x
-                                    const double2 vx = S.P[m * LD + c];
-                                    const double2 w = c_make(hbr[ti][tj][q] + rr * vx.y, hbi[ti][tj][q] - rr * vx.x);
-                                    const double2 h1 = c_mul(pc, w);
-                                    bad |= !isfinite(h1.x + h1.y);
-                                    const long long e = (long long)m * n + c;
-                                    ph_[e] = (kk == 0) ? h1 : c_add(ph_[e], h1);
-                                }
-                            }
-                }
+                        for (int q = 0; q < 4; ++q) {
+                            const int m = 16 * ti + g + 4 * q, c = 16 * tj + c16;
+                            if (m < n && c < n) Xk[(long long)m * n + c] = c_make(hbr[ti][tj][q], hbi[ti][tj][q]);
+                        }
             }
-            // ---- vbar_y = U Bbar U^+ -> PY
             {
                 v4d yr[NT][NT], yi[NT][NT];
 #pragma unroll
@@ -1403,26 +1391,16 @@ __global__ __launch_bounds__(64) void k_adjoint_wave(WgLaunch a) {
                         }
                 v4d vyr[NT][NT], vyi[NT][NT];
                 wave_sandwich<NP>(yr, yi, ua, vyr, vyi);
-                for (int rho = 0; rho < md.nR0; ++rho) {
-                    const double2 pc = c_conj(S.ph[rho]);
-                    double2* py_ = PY + (long long)rho * nn;
 #pragma unroll
-                    for (int ti = 0; ti < NT; ++ti)
+                for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
-                        for (int tj = 0; tj < NT; ++tj)
+                    for (int tj = 0; tj < NT; ++tj)
 #pragma unroll
-                            for (int q = 0; q < 4; ++q) {
-                                const int m = 16 * ti + g + 4 * q, c = 16 * tj + c16;
-                                if (m < n && c < n) {
-                                    const double2 y1 = c_mul(pc, c_make(vyr[ti][tj][q], vyi[ti][tj][q]));
-                                    bad |= !isfinite(y1.x + y1.y);
-                                    const long long e = (long long)m * n + c;
-                                    py_[e] = (kk == 0) ? y1 : c_add(py_[e], y1);
-                                }
-                            }
-                }
+                        for (int q = 0; q < 4; ++q) {
+                            const int m = 16 * ti + g + 4 * q, c = 16 * tj + c16;
+                            if (m < n && c < n) Xk[2 * nn + (long long)m * n + c] = c_make(vyr[ti][tj][q], vyi[ti][tj][q]);
+                        }
             }
-            if (__ballot(bad) != 0ull && lane == 0) atomicOr(a.status, kStatNonFinite);
             __syncthreads();
         }
     }
