@@ -272,7 +272,9 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
     P->n_slots = slot;
 
     // chunks: consecutive pencils while the T region stays under the cap (and, backward,
-    // the per-block pencil partials under four times the cap)
+    // the per-block pencil partials plus the per-k adjoint matrices under sixteen
+    // times the cap: enough work per launch that the last round of the
+    // persistent grid is a small fraction)
     auto chunkify = [&](bool with_p, kubo_plan_s::ChunkSet& cs) {
         Chunk cur;
         std::vector<std::vector<BlockItem>> cls_blocks(kNumClasses);
@@ -324,7 +326,7 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
             PB pb = pb0;
             if (cur.pencil_count > 0 &&
                 (cur.tbytes + pb.tbytes > cap ||
-                 (with_p && cur.pbytes + cur.xbytes + pb.pbytes + pb.xbytes > 4 * cap)))
+                 (with_p && cur.pbytes + cur.xbytes + pb.pbytes + pb.xbytes > 16 * cap)))
                 flush();
             PencilItem pi = pb.pi;
             pi.tbuf_off = (long long)(cur.tbytes / 16);
