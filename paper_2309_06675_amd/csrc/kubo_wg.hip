@@ -408,20 +408,34 @@ __device__ bool wg_ql(WgLds& S, double2* __restrict__ Z, int n, int max_iter) {
 }
 
 // ---------------------------------------------------------------------------
-// step 2d: U <- H_0 ... H_{n-2} U (thread c owns column c)
+// step 2d: U <- H_0 ... H_{n-2} U.  G consecutive threads share a column
+// (G = the largest power of two with G n <= 256), each taking every G-th row;
+// the reflector is staged in LDS once per step and the partial products are
+// combined across the G lanes.
 // ---------------------------------------------------------------------------
 __device__ void wg_backtransform(WgLds& S, const double2* __restrict__ P, double2* __restrict__ U,
                                  int n) {
-    const int c = threadIdx.x;
-    if (c < n) {
-        for (int k = n - 2; k >= 0; --k) {
-            const double2 tau = S.tau[k];
-            if (tau.x == 0.0 && tau.y == 0.0) continue;
-            double2 y = c_make(0.0, 0.0);
-            for (int r = k + 1; r < n; ++r) y = c_fmac(P[r * n + k], U[r * n + c], y);
-            const double2 ty = c_mul(tau, y);
-            for (int r = k + 1; r < n; ++r) U[r * n + c] = c_sub(U[r * n + c], c_mul(P[r * n + k], ty));
+    int G = 1;
+    while (2 * G * n <= kWgThreads && G < 64) G *= 2;
+    const int tid = threadIdx.x;
+    const int c = tid / G, g = tid - c * G;
+    const bool act = c < n;
+    for (int k = n - 2; k >= 0; --k) {
+        const double2 tau = S.tau[k];
+        if (tau.x == 0.0 && tau.y == 0.0) continue;
+        for (int r = k + 1 + tid; r < n; r += kWgThreads) S.vv[r] = P[r * n + k];
+        __syncthreads();
+        double2 y = c_make(0.0, 0.0);
+        if (act)
+            for (int r = k + 1 + g; r < n; r += G) y = c_fmac(S.vv[r], U[r * n + c], y);
+        for (int off = 1; off < G; off <<= 1) {
+            y.x += __shfl_xor(y.x, off, 64);
+            y.y += __shfl_xor(y.y, off, 64);
         }
+        const double2 ty = c_mul(tau, y);
+        if (act)
+            for (int r = k + 1 + g; r < n; r += G) U[r * n + c] = c_sub(U[r * n + c], c_mul(S.vv[r], ty));
+        __syncthreads();
     }
     __syncthreads();
 }
