@@ -139,48 +139,76 @@ __global__ __launch_bounds__(kPencilThreads) void k_pencil(Tables tb, int item_b
 // for one range of k-blocks of one model (fixed order over the blocks).
 // Grid: x = lattice vector in grouped order, y = tile of matrix entries, z = range.
 // ---------------------------------------------------------------------------
-constexpr int kGaccThreads = 256;
+constexpr int kGaccThreads = 128;
+constexpr int kGaccRB = 4;      // lattice vectors of one R_x group per workgroup
+constexpr int kGaccBlocks = 64; // k-blocks whose phases sit in LDS at a time
+
+// G(R) += sum_blocks e^{-i(k1 R_y + k2 R_z)} (PH_rho - i R_y PY_rho) for a batch of up to
+// kGaccRB lattice vectors sharing R_x = rho: each block's PH_rho, PY_rho element is read
+// once and serves the whole batch (small batches and element tiles keep enough
+// workgroups in flight).  Grid: (rho, batch) x element tiles x block ranges.
 __global__ __launch_bounds__(kGaccThreads) void k_gacc(Tables tb, const GaccRange* __restrict__ ranges,
-                                                       int range_begin,
+                                                       int range_begin, int nbatch,
                                                        const double2* __restrict__ pbuf,
                                                        double2* __restrict__ grad) {
-    __shared__ double2 sph[kGaccThreads];
-    __shared__ long long soff[kGaccThreads];
+    __shared__ double2 sph[kGaccRB][kGaccBlocks];
+    __shared__ long long soff[kGaccBlocks];
     const GaccRange rg = ranges[range_begin + blockIdx.z];
     const ModelDev md = tb.models[rg.model];
-    const int g = blockIdx.x;
-    if (g >= md.nR) return;
+    const int rho = (int)blockIdx.x / nbatch, batch = (int)blockIdx.x - rho * nbatch;
+    if (rho >= md.nR0) return;
+    const int* gs = tb.grp_start + md.gs_first;
+    const int g0 = gs[rho] + batch * kGaccRB;
+    const int g1 = min(gs[rho + 1], g0 + kGaccRB);
+    if (g0 >= g1) return;
+    const int nb = g1 - g0;
     const int n = md.n;
     const long long nn = (long long)n * n;
-    const int gi = md.grp_first + g;
-    const int r = tb.grp_r[gi];
-    const int R1 = tb.grp_R1[gi], R2 = tb.grp_R2[gi];
-    const int rho = tb.grp_rho[gi];
-    const long long e = (long long)blockIdx.y * kGaccThreads + threadIdx.x;
     if ((long long)blockIdx.y * kGaccThreads >= nn) return;
-    double2 acc = c_make(0.0, 0.0);
-    for (int b0 = 0; b0 < rg.count; b0 += kGaccThreads) {
-        const int bc = min(kGaccThreads, rg.count - b0);
+    const long long e = (long long)blockIdx.y * kGaccThreads + threadIdx.x;
+    int R1[kGaccRB];
+#pragma unroll
+    for (int q = 0; q < kGaccRB; ++q) R1[q] = (q < nb) ? tb.grp_R1[md.grp_first + g0 + q] : 0;
+    double2 acc[kGaccRB];
+#pragma unroll
+    for (int q = 0; q < kGaccRB; ++q) acc[q] = c_make(0.0, 0.0);
+    for (int b0 = 0; b0 < rg.count; b0 += kGaccBlocks) {
+        const int bc = min(kGaccBlocks, rg.count - b0);
         __syncthreads();
-        if (threadIdx.x < bc) {
-            const BlockItem bi = tb.blocks[rg.begin + b0 + threadIdx.x];
-            sph[threadIdx.x] = unit_phase2(-(long long)bi.i1 * R1, md.N1, -(long long)bi.i2 * R2, md.N2);
-            soff[threadIdx.x] = bi.pbuf_off;
+        for (int idx = threadIdx.x; idx < bc * nb; idx += kGaccThreads) {
+            const int q = idx / bc, b = idx - q * bc;
+            const BlockItem bi = tb.blocks[rg.begin + b0 + b];
+            const int gi = md.grp_first + g0 + q;
+            sph[q][b] = unit_phase2(-(long long)bi.i1 * tb.grp_R1[gi], md.N1,
+                                    -(long long)bi.i2 * tb.grp_R2[gi], md.N2);
+            if (q == 0) soff[b] = bi.pbuf_off;
         }
         __syncthreads();
         if (e < nn) {
+#pragma unroll 4
             for (int b = 0; b < bc; ++b) {
                 const double2* P = pbuf + soff[b];
                 const double2 h = P[(long long)rho * nn + e];
                 const double2 y = P[(long long)(md.nR0 + rho) * nn + e];
-                const double2 w = c_sub(h, c_scale((double)R1, c_i(y)));
-                acc = c_fma(sph[b], w, acc);
+#pragma unroll
+                for (int q = 0; q < kGaccRB; ++q) {
+                    if (q < nb) {
+                        const double2 w = c_sub(h, c_scale((double)R1[q], c_i(y)));
+                        acc[q] = c_fma(sph[q][b], w, acc[q]);
+                    }
+                }
             }
         }
     }
     if (e < nn) {
-        double2* G = grad + md.t_off + (long long)r * nn + e;
-        *G = c_add(*G, acc);
+#pragma unroll
+        for (int q = 0; q < kGaccRB; ++q) {
+            if (q < nb) {
+                const int r = tb.grp_r[md.grp_first + g0 + q];
+                double2* G = grad + md.t_off + (long long)r * nn + e;
+                *G = c_add(*G, acc[q]);
+            }
+        }
     }
 }
 
@@ -361,12 +389,13 @@ hipError_t launch_pacc(const Tables& tb, int begin, int count, long long max_nn,
 }
 
 hipError_t launch_gacc(const Tables& tb, const GaccRange* ranges, int range_begin, int range_count,
-                       int max_nR, long long max_nn, const double* pbuf, double* grad,
+                       int max_group, long long max_nn, const double* pbuf, double* grad,
                        hipStream_t s) {
     if (range_count <= 0) return hipSuccess;
+    const int nbatch = (max_group + kGaccRB - 1) / kGaccRB;
     const unsigned ty = (unsigned)((max_nn + kGaccThreads - 1) / kGaccThreads);
-    hipLaunchKernelGGL(k_gacc, dim3(max_nR, ty, range_count), dim3(kGaccThreads), 0, s, tb,
-                       ranges, range_begin, reinterpret_cast<const double2*>(pbuf),
+    hipLaunchKernelGGL(k_gacc, dim3(kMaxR0 * nbatch, ty, range_count), dim3(kGaccThreads), 0, s, tb,
+                       ranges, range_begin, nbatch, reinterpret_cast<const double2*>(pbuf),
                        reinterpret_cast<double2*>(grad));
     return hipGetLastError();
 }

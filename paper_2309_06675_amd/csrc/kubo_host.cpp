@@ -109,6 +109,7 @@ struct kubo_plan_s {
     const void* uploaded_ws = nullptr;
     CachedGraph graph_fwd, graph_bwd;
     int max_groups = 2048;
+    int max_group = 1;  // most lattice vectors sharing one R_x value
     // KUBO_F_TIMING: event pairs around per-k kernel launches
     struct TimeRec {
         int which;
@@ -191,6 +192,7 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
         md.grp_first = (int)P->grp_r.size();
         int acc = 0;
         for (int xi = 0; xi < (int)xs.size(); ++xi) {
+            const int acc0 = acc;
             P->grp_start.push_back(acc);
             for (int r = 0; r < d.n_R; ++r)
                 if (d.R[3 * r] == xs[xi]) {
@@ -200,6 +202,7 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
                     P->grp_rho.push_back(xi);
                     ++acc;
                 }
+            P->max_group = std::max(P->max_group, acc - acc0);
         }
         P->max_nR = std::max(P->max_nR, d.n_R);
         P->max_nn = std::max(P->max_nn, (long long)d.n_orb * d.n_orb);
@@ -603,7 +606,7 @@ kubo_status enqueue_backward(kubo_plan_s* P, const double* t, const double* ef, 
             if (kClasses[k].wave)
                 HIP_TRY(launch_pacc(tb, c.cls[k].begin, c.cls[k].count, P->max_nn, xbuf, pbuf, status, s));
         }
-        HIP_TRY(launch_gacc(tb, tb.granges, c.grange_begin, c.grange_count, P->max_nR, P->max_nn,
+        HIP_TRY(launch_gacc(tb, tb.granges, c.grange_begin, c.grange_count, P->max_group, P->max_nn,
                             pbuf, grad, s));
     }
     HIP_TRY(launch_gsym(tb, P->n_models, P->t_elems, grad, s));

@@ -56,8 +56,9 @@ hipError_t launch_forward_wave(const FwdLaunch& L, hipStream_t s);
 // PH_rho = sum_k e^{-i k0 rho}(Hbar - i rho vbar_x), PY_rho = sum_k e^{-i k0 rho} vbar_y
 hipError_t launch_pacc(const Tables& tb, int begin, int count, long long max_nn, const double* xbuf,
                        double* pbuf, unsigned* status, hipStream_t s);
+// max_group: the largest number of lattice vectors sharing one R_x value
 hipError_t launch_gacc(const Tables& tb, const GaccRange* ranges, int range_begin, int range_count,
-                       int max_nR, long long max_nn, const double* pbuf, double* grad,
+                       int max_group, long long max_nn, const double* pbuf, double* grad,
                        hipStream_t s);
 hipError_t launch_gsym(const Tables& tb, int n_models, long long total, double* grad,
                        hipStream_t s);
