@@ -80,6 +80,32 @@ def test_gradient_slab_and_symmetry(torch, oracle):
         assert np.array_equal(G[idx[tuple(-v)]], G[i].conj().T)
 
 
+def test_mixed_models_many_chunks_backward(torch, oracle, monkeypatch):
+    """Three models in one plan, one per adjoint kernel (n = 7 runs the one-wavefront kernel
+    at NP = 16, n = 21 at NP = 32, n = 37 the workgroup kernel), on grids long enough in k_x
+    for several backward k-blocks per pencil.  With 1 MB chunks every launch holds a few
+    pencils, so the per-k adjoint store, the block pencil sums and the gradient accumulation
+    all run across many chunk boundaries; the result must match the single-chunk plan, the
+    per-model plans and the oracle."""
+    models = [synth.random_model(n, 1, 1.0, 5150 + n) for n in (7, 21, 37)]
+    grid = (70, 2, 2)
+    ef = np.array([-1.5, 0.3])
+    sbar = np.array([0.8, -1.1])
+    one, *_ = gpu_grad(torch, models, grid, ef, 0.03, 0.02, sbar)
+    monkeypatch.setenv("KUBO_CHUNK_MB", "1")
+    many, plan, *_ = gpu_grad(torch, models, grid, ef, 0.03, 0.02, sbar)
+    monkeypatch.delenv("KUBO_CHUNK_MB")
+    assert_grad_close(many, one, 1e-12, "many chunks vs one")
+    off = 0
+    for m in models:
+        alone, *_ = gpu_grad(torch, [m], grid, ef, 0.03, 0.02, sbar)
+        cnt = m.t.size
+        assert_grad_close(one[off:off + cnt], alone, 1e-12, f"n={m.n} in the mixed plan vs alone")
+        ref = oracle.ahc_grad(m.t, m.R, grid, ef, 0.03, 0.02, sbar)
+        assert_grad_close(alone, ref.reshape(-1), 1e-9, f"n={m.n} vs oracle")
+        off += cnt
+
+
 def test_cfg3_model_oracle_gradient_on_8cubed(torch, oracle):
     wl = synth.workload(3)
     m = wl.models[0]
