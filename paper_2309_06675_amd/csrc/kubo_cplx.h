@@ -67,6 +67,17 @@ __device__ __forceinline__ double occupation(double e, double ef, double kT) {
     return (u > 0.0) ? w * r : r;
 }
 
+// The same with 1/kT supplied (a multiplication instead of a division per call).
+__device__ __forceinline__ double occupation_ikt(double e, double ef, double kT, double ikT) {
+    if (kT == 0.0) return e < ef ? 1.0 : (e > ef ? 0.0 : 0.5);
+    const double u = (e - ef) * ikT;
+    const double w = exp(-fabs(u));
+    const double d = 1.0 + w;
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    return (u > 0.0) ? w * r : r;
+}
+
 // conj(a) * b  and  a * conj(b)
 __device__ __forceinline__ double2 c_cmul(double2 a, double2 b) {
     return c_make(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);

@@ -954,10 +954,11 @@ __global__ __launch_bounds__(64) void k_forward_wave(FwdLaunch a) {
                 if (i < n && (lane & 1) == 0) S.Om[i] = -2.0 * om;
             }
             __syncthreads();
+            const double ikT = (a.kT > 0.0) ? 1.0 / a.kT : 0.0;
             for (int j = lane; j < a.nF; j += 64) {
                 const double efj = ef[j];
                 double s = 0.0;
-                for (int b = 0; b < n; ++b) s += occupation(S.E[b], efj, a.kT) * S.Om[b];
+                for (int b = 0; b < n; ++b) s += occupation_ikt(S.E[b], efj, a.kT, ikT) * S.Om[b];
                 if (!isfinite(s)) atomicOr(a.status, kStatNonFinite);
                 part[j] = (kk == 0) ? s : part[j] + s;
             }
@@ -1018,19 +1019,21 @@ __device__ __forceinline__ void wave_phi_at(double x, const double* __restrict__
                                             const double* __restrict__ sb, int nF, double kT,
                                             double& phi, double& dphi) {
     double p = 0.0, d = 0.0;
-    for (int j = 0; j < nF; ++j) {
-        if (kT > 0.0) {
-            const double u = (x - ef[j]) / kT;
+    if (kT > 0.0) {
+        const double ikT = 1.0 / kT;
+#pragma unroll 4
+        for (int j = 0; j < nF; ++j) {
+            const double u = (x - ef[j]) * ikT;
             const double w = exp(-fabs(u));
             const double dd = 1.0 + w;
             double r = __builtin_amdgcn_rcp(dd);
             r = fma(r, fma(-dd, r, 1.0), r);
             const double f = (u > 0.0) ? w * r : r;
             p += sb[j] * f;
-            d -= sb[j] * (w * r * r) / kT;  // f (1 - f) / kT = w / (1 + w)^2 / kT
-        } else {
-            p += sb[j] * occupation(x, ef[j], kT);
+            d -= sb[j] * (w * r * r) * ikT;  // f (1 - f) / kT = w / (1 + w)^2 / kT
         }
+    } else {
+        for (int j = 0; j < nF; ++j) p += sb[j] * occupation(x, ef[j], kT);
     }
     phi = p;
     dphi = d;
