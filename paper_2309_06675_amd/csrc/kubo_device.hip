@@ -300,7 +300,8 @@ hipError_t launch_hermproj(const Tables& tb, int n_models, long long total, cons
 }
 
 // ---------------------------------------------------------------------------
-// k_pacc: pencil sums of the one-wavefront adjoint's per-k matrices, one
+// k_pacc: pencil sums of the one-wavefront adjoint's per-k matrices (Hermitian,
+// upper triangle stored; the lower one is read as the conjugate transpose), one
 // workgroup per (k-block, 256 matrix elements).  For each R_x value rho:
 //   PH_rho = sum_k e^{-i k0 rho} (Hbar - i rho vbar_x),  PY_rho = sum_k e^{-i k0 rho} vbar_y,
 // summed over the block's k-points in order.  The phases of up to 32
@@ -318,6 +319,10 @@ __global__ __launch_bounds__(kPaccThreads) void k_pacc(Tables tb, int begin, con
     if ((long long)blockIdx.y * kPaccThreads >= nn) return;  // whole workgroup past this matrix
     const long long e = (long long)blockIdx.y * kPaccThreads + threadIdx.x;
     const bool act = e < nn;
+    // the per-k matrices are Hermitian and only their upper triangle is stored
+    const int em = act ? (int)(e / md.n) : 0, ec = act ? (int)(e - (long long)em * md.n) : 0;
+    const bool lower = em > ec;
+    const long long es = lower ? (long long)ec * md.n + em : e;
     const int nR0 = md.nR0;
     const int* r0 = tb.r0val + md.r0_first;
     const double2* X = xbuf + it.xbuf_off;
@@ -338,7 +343,12 @@ __global__ __launch_bounds__(kPaccThreads) void k_pacc(Tables tb, int begin, con
         if (act) {
             for (int kk = 0; kk < kc; ++kk) {
                 const double2* Xk = X + (long long)(k0 + kk) * 3 * nn;
-                const double2 h = Xk[e], vx = Xk[nn + e], vy = Xk[2 * nn + e];
+                double2 h = Xk[es], vx = Xk[nn + es], vy = Xk[2 * nn + es];
+                if (lower) {
+                    h = c_conj(h);
+                    vx = c_conj(vx);
+                    vy = c_conj(vy);
+                }
                 const bool first = (k0 + kk == 0);
 #pragma unroll
                 for (int rho = 0; rho < kMaxR0; ++rho) {

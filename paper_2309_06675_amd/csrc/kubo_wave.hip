@@ -1351,8 +1351,9 @@ __global__ __launch_bounds__(64) void k_adjoint_wave(WgLaunch a) {
                         S.U[(16 * ti + g + 4 * q) * LD + 16 * tj + c16] =
                             c_make(kv * ai[ti][tj][q], -kv * ar[ti][tj][q]);
                     }
-            // ---- vbar_x = U Abar U^+, Hbar = U Hbar' U^+, vbar_y = U Bbar U^+, stored for
-            // this k-point (the pencil sums over the block are taken by a separate pass)
+            // ---- vbar_x = U Abar U^+, Hbar = U Hbar' U^+, vbar_y = U Bbar U^+ (all three
+            // Hermitian: the upper triangle is stored for this k-point; the pencil sums
+            // over the block are taken by a separate pass)
             double2* Xk = xb + it.xbuf_off + (long long)kk * 3 * nn;
             {
                 v4d vr_[NT][NT], vi_[NT][NT];
@@ -1364,7 +1365,7 @@ __global__ __launch_bounds__(64) void k_adjoint_wave(WgLaunch a) {
 #pragma unroll
                         for (int q = 0; q < 4; ++q) {
                             const int m = 16 * ti + g + 4 * q, c = 16 * tj + c16;
-                            if (m < n && c < n) Xk[nn + (long long)m * n + c] = c_make(vr_[ti][tj][q], vi_[ti][tj][q]);
+                            if (m <= c && c < n) Xk[nn + (long long)m * n + c] = c_make(vr_[ti][tj][q], vi_[ti][tj][q]);
                         }
             }
             {
@@ -1377,7 +1378,7 @@ __global__ __launch_bounds__(64) void k_adjoint_wave(WgLaunch a) {
 #pragma unroll
                         for (int q = 0; q < 4; ++q) {
                             const int m = 16 * ti + g + 4 * q, c = 16 * tj + c16;
-                            if (m < n && c < n) Xk[(long long)m * n + c] = c_make(hbr[ti][tj][q], hbi[ti][tj][q]);
+                            if (m <= c && c < n) Xk[(long long)m * n + c] = c_make(hbr[ti][tj][q], hbi[ti][tj][q]);
                         }
             }
             {
@@ -1401,7 +1402,7 @@ __global__ __launch_bounds__(64) void k_adjoint_wave(WgLaunch a) {
 #pragma unroll
                         for (int q = 0; q < 4; ++q) {
                             const int m = 16 * ti + g + 4 * q, c = 16 * tj + c16;
-                            if (m < n && c < n) Xk[2 * nn + (long long)m * n + c] = c_make(vyr[ti][tj][q], vyi[ti][tj][q]);
+                            if (m <= c && c < n) Xk[2 * nn + (long long)m * n + c] = c_make(vyr[ti][tj][q], vyi[ti][tj][q]);
                         }
             }
             __syncthreads();
