@@ -145,10 +145,16 @@ __device__ void wave_tridiag(WaveLds<NP>& S, int n, double& d_lane, double& e_la
     e_lane = 0.0;
     for (int k = 0; k < n - 1; ++k) {
         const int hk = k & 1, jk = k >> 1;  // lane half and slot holding column k
+        // a[jk]: a wave-uniform branch picks the group of four slots, a select the slot
         double2 xk = c_make(0.0, 0.0);
 #pragma unroll
-        for (int jj = 0; jj < HW; ++jj)
-            if (jj == jk) xk = a[jj];
+        for (int gq = 0; gq < HW / 4; ++gq) {
+            if ((jk >> 2) == gq) {
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    if ((jk & 3) == t) xk = a[4 * gq + t];
+            }
+        }
         const bool own = (h == hk);
         const double2 xp = c_make(dpp_xor1(xk.x), dpp_xor1(xk.y));
         const double2 x = own ? xk : xp;  // A[i][k] in both lanes of row i
@@ -183,8 +189,13 @@ __device__ void wave_tridiag(WaveLds<NP>& S, int n, double& d_lane, double& e_la
         }
         // the reflector replaces column k below the diagonal
 #pragma unroll
-        for (int jj = 0; jj < HW; ++jj)
-            if (own && jj == jk && i > k) a[jj] = v;
+        for (int gq = 0; gq < HW / 4; ++gq) {
+            if ((jk >> 2) == gq) {
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    if (own && (jk & 3) == t && i > k) a[4 * gq + t] = v;
+            }
+        }
         if (lane == 0) S.tau[k] = tau;
         if (h == 0 && i < NP) S.vv[i] = v;
         __syncthreads();
