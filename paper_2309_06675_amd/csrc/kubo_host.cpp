@@ -23,15 +23,15 @@ namespace {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-// Size classes of the forward per-k kernel: one wavefront per k-point with the
-// matrices padded to np (n <= 32), or one workgroup per k-point with the
-// matrices in workspace scratch (np = 128 marks that class).  The adjoint
-// always uses the workgroup kernel.
+// Size classes of the per-k kernels (forward and adjoint alike): one wavefront
+// per k-point with the matrices padded to np (n <= 32), or one workgroup per
+// k-point with the matrices in workspace scratch (n <= 64: register
+// back-transformation at two waves per SIMD; n <= 128: the LDS-staged one).
 struct ClassInfo {
     int np;
     bool wave;
 };
-const ClassInfo kClasses[] = {{8, true}, {16, true}, {32, true}, {128, false}};
+const ClassInfo kClasses[] = {{8, true}, {16, true}, {32, true}, {64, false}, {128, false}};
 constexpr int kNumClasses = sizeof(kClasses) / sizeof(kClasses[0]);
 
 int class_of(int n) {
@@ -225,7 +225,14 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
         const int nbb = (d.grid[0] + 31) / 32;
         const int kblock_b = std::max(kblock, (d.grid[0] + nbb - 1) / nbb);
         int cls = class_of(d.n_orb);
-        if (ti != tile_of.end() && ti->second.threads == 256) cls = kNumClasses - 1;
+        if (ti != tile_of.end() && ti->second.threads == 256) {
+            // the workgroup kernel forced: its smallest class that holds n
+            for (int c2 = 0; c2 < kNumClasses; ++c2)
+                if (!kClasses[c2].wave && d.n_orb <= kClasses[c2].np) {
+                    cls = c2;
+                    break;
+                }
+        }
         md.slot_first = slot;
         const long long nn = (long long)d.n_orb * d.n_orb;
         const size_t mat_bytes = (size_t)2 * md.nR0 * nn * 16;
@@ -550,7 +557,7 @@ kubo_status enqueue_forward(kubo_plan_s* P, const double* t, const double* ef, d
                 L.item_begin = c.cls[k].begin;
                 L.item_count = c.cls[k].count;
                 L.max_groups = P->wg_groups;
-                HIP_TRY(launch_forward_wg(L, s));
+                HIP_TRY(launch_forward_wg(L, kClasses[k].np, s));
             }
             ts.finish();
         }
@@ -600,7 +607,7 @@ kubo_status enqueue_backward(kubo_plan_s* P, const double* t, const double* ef, 
                 L.max_groups = P->max_groups;
                 HIP_TRY(launch_adjoint_wave(L, kClasses[k].np, s));
             } else {
-                HIP_TRY(launch_adjoint_wg(L, s));
+                HIP_TRY(launch_adjoint_wg(L, kClasses[k].np, s));
             }
             ts.finish();
             if (kClasses[k].wave)

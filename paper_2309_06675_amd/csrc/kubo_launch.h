@@ -40,8 +40,9 @@ struct WgLaunch {
 };
 
 long long wg_slot_elems(int nmax);
-hipError_t launch_forward_wg(const WgLaunch& L, hipStream_t s);
-hipError_t launch_adjoint_wg(const WgLaunch& L, hipStream_t s);
+// np: the size class (64: n <= 64, 128: n <= 128)
+hipError_t launch_forward_wg(const WgLaunch& L, int np, hipStream_t s);
+hipError_t launch_adjoint_wg(const WgLaunch& L, int np, hipStream_t s);
 // one wavefront per k-point for n <= 32 (np: the size class, 8, 16 or 32)
 hipError_t launch_adjoint_wave(const WgLaunch& L, int np, hipStream_t s);
 

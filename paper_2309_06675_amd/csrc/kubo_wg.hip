@@ -259,13 +259,18 @@ __device__ void wg_bisect(WgLds& S, int n, double& pivmin_out, double& span_out)
 __device__ void wg_twisted(WgLds& S, const WgScratch& X, int n, double pivmin) {
     const int j = threadIdx.x;
     const long long nn = (long long)n * n;
+    // reciprocal: hardware estimate and one Newton step (|q| >= pivmin keeps it finite)
+    auto rcp = [](double q) {
+        const double r0 = __builtin_amdgcn_rcp(q);
+        return fma(r0, fma(-q, r0, 1.0), r0);
+    };
     if (j < n) {
         const double lam = S.lam[j];
         double* dp = X.DPM;
         double* dm = X.DPM + nn;
         double qv = 1.0, e2prev = 0.0;
         for (int i = 0; i < n; ++i) {
-            double qi = (S.d[i] - lam) - e2prev / qv;
+            double qi = (S.d[i] - lam) - e2prev * rcp(qv);
             if (fabs(qi) < pivmin) qi = -pivmin;
             dp[(long long)i * n + j] = qi;
             qv = qi;
@@ -275,7 +280,7 @@ __device__ void wg_twisted(WgLds& S, const WgScratch& X, int n, double pivmin) {
         int r = 0;
         double best = 1e308, gam = 0.0;
         for (int i = n - 1; i >= 0; --i) {
-            double qi = (S.d[i] - lam) - ((i < n - 1) ? S.e[i] * S.e[i] / qv : 0.0);
+            double qi = (S.d[i] - lam) - ((i < n - 1) ? S.e[i] * S.e[i] * rcp(qv) : 0.0);
             if (fabs(qi) < pivmin) qi = -pivmin;
             dm[(long long)i * n + j] = qi;
             qv = qi;
@@ -290,13 +295,13 @@ __device__ void wg_twisted(WgLds& S, const WgScratch& X, int n, double pivmin) {
         X.U[(long long)r * n + j] = c_make(1.0, 0.0);
         double z = 1.0;
         for (int i = r - 1; i >= 0; --i) {
-            z = -(S.e[i] / dp[(long long)i * n + j]) * z;
+            z = -(S.e[i] * rcp(dp[(long long)i * n + j])) * z;
             X.U[(long long)i * n + j] = c_make(z, 0.0);
             nrm += z * z;
         }
         z = 1.0;
         for (int i = r + 1; i < n; ++i) {
-            z = -(S.e[i - 1] / dm[(long long)i * n + j]) * z;
+            z = -(S.e[i - 1] * rcp(dm[(long long)i * n + j])) * z;
             X.U[(long long)i * n + j] = c_make(z, 0.0);
             nrm += z * z;
         }
@@ -413,6 +418,69 @@ __device__ bool wg_ql(WgLds& S, double2* __restrict__ Z, int n, int max_iter) {
 // the reflector is staged in LDS once per step and the partial products are
 // combined across the G lanes.
 // ---------------------------------------------------------------------------
+// n <= 64: U's column c in registers, four threads per column (rows 4 jj + g),
+// the reflectors staged into LDS sixteen columns at a time, and groups of four
+// row slots that lie above the reflector skipped by a wave-uniform test.
+__device__ void wg_backtransform_reg(WgLds& S, const double2* __restrict__ P, double2* __restrict__ U,
+                                     int n) {
+    constexpr int G = 4, RJ = 16, KC = 16;
+    const int tid = threadIdx.x;
+    const int c = tid >> 2, g = tid & 3;
+    const bool act = c < n;
+    double2* V = S.ta;  // [KC][64]: reflector columns k0 .. k0+KC-1
+    double2 u[RJ];
+#pragma unroll
+    for (int jj = 0; jj < RJ; ++jj) {
+        const int r = G * jj + g;
+        u[jj] = (act && r < n) ? U[r * n + c] : c_make(0.0, 0.0);
+    }
+    for (int k1 = n - 1; k1 > 0; k1 -= KC) {
+        const int k0 = (k1 - KC > 0) ? k1 - KC : 0;  // this chunk: reflectors k0 .. k1-1
+        __syncthreads();
+        for (int e = tid; e < (k1 - k0) * 64; e += kWgThreads) {
+            const int kk = e >> 6, r = e & 63;
+            const int k = k0 + kk;
+            V[kk * 64 + r] = (r > k && r < n) ? P[r * n + k] : c_make(0.0, 0.0);
+        }
+        __syncthreads();
+        for (int k = k1 - 1; k >= k0; --k) {
+            const double2 tau = S.tau[k];
+            if (tau.x == 0.0 && tau.y == 0.0) continue;
+            const double2* v = V + (k - k0) * 64;
+            double2 y = c_make(0.0, 0.0);
+#pragma unroll
+            for (int gq = 0; gq < RJ / 4; ++gq) {
+                if (16 * gq + 15 > k) {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) y = c_fmac(v[G * (4 * gq + t) + g], u[4 * gq + t], y);
+                }
+            }
+            y.x += __shfl_xor(y.x, 1, 64);
+            y.y += __shfl_xor(y.y, 1, 64);
+            y.x += __shfl_xor(y.x, 2, 64);
+            y.y += __shfl_xor(y.y, 2, 64);
+            const double2 ty = c_mul(tau, y);
+#pragma unroll
+            for (int gq = 0; gq < RJ / 4; ++gq) {
+                if (16 * gq + 15 > k) {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const int jj = 4 * gq + t;
+                        u[jj] = c_sub(u[jj], c_mul(v[G * jj + g], ty));
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int jj = 0; jj < RJ; ++jj) {
+        const int r = G * jj + g;
+        if (act && r < n) U[r * n + c] = u[jj];
+    }
+    __syncthreads();
+}
+
 __device__ void wg_backtransform(WgLds& S, const double2* __restrict__ P, double2* __restrict__ U,
                                  int n) {
     int G = 1;
@@ -485,6 +553,7 @@ __device__ void wg_gemm(WgLds& S, double2* __restrict__ C, int n, FA LA, FB LB) 
 }
 
 // Steps 1-3: E (S.E), U, and A = U^+ v_x U in X.VX, B = U^+ v_y U in X.VY.
+template <bool SMALL>
 __device__ bool wg_eigen_velocities(WgLds& S, const WgScratch& X, const ModelDev& md,
                                     const double2* __restrict__ T0, const double2* __restrict__ T1,
                                     const int* __restrict__ r0, int i0, int max_iter) {
@@ -508,7 +577,10 @@ __device__ bool wg_eigen_velocities(WgLds& S, const WgScratch& X, const ModelDev
     } else {
         ok = wg_ql(S, X.U, n, max_iter);
     }
-    wg_backtransform(S, X.P, X.U, n);
+    if constexpr (SMALL)
+        wg_backtransform_reg(S, X.P, X.U, n);
+    else
+        wg_backtransform(S, X.P, X.U, n);
     const double2* U = X.U;
     double2* W = X.W;
     double2* VX = X.VX;
@@ -527,7 +599,9 @@ __device__ bool wg_eigen_velocities(WgLds& S, const WgScratch& X, const ModelDev
 // ---------------------------------------------------------------------------
 // k_forward_wg
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kWgThreads) void k_forward_wg(WgLaunch a) {
+// SMALL (n <= 64): register back-transformation, two waves per SIMD
+template <bool SMALL>
+__global__ __launch_bounds__(kWgThreads, SMALL ? 2 : 1) void k_forward_wg(WgLaunch a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     WgLds& S = *reinterpret_cast<WgLds*>(smem_raw);
     const double eta2 = a.eta * a.eta;
@@ -545,7 +619,7 @@ __global__ __launch_bounds__(kWgThreads) void k_forward_wg(WgLaunch a) {
         const double* ef = a.e_fermi + md.f_off;
         double* part = a.partial + (long long)it.slot * a.nF;
         for (int kk = 0; kk < it.count; ++kk) {
-            const bool ok = wg_eigen_velocities(S, X, md, T0, T1, r0, it.i0 + kk, a.max_iter);
+            const bool ok = wg_eigen_velocities<SMALL>(S, X, md, T0, T1, r0, it.i0 + kk, a.max_iter);
             if (!ok) atomicOr(a.status, kStatNoConv);
             for (int i = threadIdx.x; i < n; i += kWgThreads) {
                 double om = 0.0;
@@ -593,7 +667,8 @@ __device__ __forceinline__ void wg_phi_at(double x, const double* __restrict__ e
 // k_adjoint_wg: reverse mode per k-point (see the one-wavefront notes in
 // kubo_device.hip for the formulas); writes the block's pencil partials.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kWgThreads) void k_adjoint_wg(WgLaunch a) {
+template <bool SMALL>
+__global__ __launch_bounds__(kWgThreads, SMALL ? 2 : 1) void k_adjoint_wg(WgLaunch a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     WgLds& S = *reinterpret_cast<WgLds*>(smem_raw);
     const double eta2 = a.eta * a.eta;
@@ -617,7 +692,7 @@ __global__ __launch_bounds__(kWgThreads) void k_adjoint_wg(WgLaunch a) {
         const double* sb = a.sbar + md.f_off;
         const double invN = 1.0 / (double)md.Nk;
         for (int kk = 0; kk < it.count; ++kk) {
-            const bool ok = wg_eigen_velocities(S, X, md, T0, T1, r0, it.i0 + kk, a.max_iter);
+            const bool ok = wg_eigen_velocities<SMALL>(S, X, md, T0, T1, r0, it.i0 + kk, a.max_iter);
             if (!ok) atomicOr(a.status, kStatNoConv);
             const double2* A = X.VX;
             const double2* B = X.VY;
@@ -718,33 +793,41 @@ __global__ __launch_bounds__(kWgThreads) void k_adjoint_wg(WgLaunch a) {
 static bool g_wg_attr = false;
 static hipError_t wg_attrs() {
     if (g_wg_attr) return hipSuccess;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_forward_wg),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(WgLds));
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_adjoint_wg),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(WgLds));
-    if (e != hipSuccess) return e;
+    const void* fns[] = {reinterpret_cast<const void*>(&k_forward_wg<true>),
+                         reinterpret_cast<const void*>(&k_forward_wg<false>),
+                         reinterpret_cast<const void*>(&k_adjoint_wg<true>),
+                         reinterpret_cast<const void*>(&k_adjoint_wg<false>)};
+    for (const void* f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(WgLds));
+        if (e != hipSuccess) return e;
+    }
     g_wg_attr = true;
     return hipSuccess;
 }
 
 long long wg_slot_elems(int nmax) { return 7LL * nmax * nmax; }
 
-hipError_t launch_forward_wg(const WgLaunch& L, hipStream_t s) {
+hipError_t launch_forward_wg(const WgLaunch& L, int np, hipStream_t s) {
     if (L.item_count <= 0) return hipSuccess;
     hipError_t e = wg_attrs();
     if (e != hipSuccess) return e;
     const int grid = L.item_count < L.max_groups ? L.item_count : L.max_groups;
-    hipLaunchKernelGGL(k_forward_wg, dim3(grid), dim3(kWgThreads), sizeof(WgLds), s, L);
+    if (np <= 64)
+        hipLaunchKernelGGL(k_forward_wg<true>, dim3(grid), dim3(kWgThreads), sizeof(WgLds), s, L);
+    else
+        hipLaunchKernelGGL(k_forward_wg<false>, dim3(grid), dim3(kWgThreads), sizeof(WgLds), s, L);
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint_wg(const WgLaunch& L, hipStream_t s) {
+hipError_t launch_adjoint_wg(const WgLaunch& L, int np, hipStream_t s) {
     if (L.item_count <= 0) return hipSuccess;
     hipError_t e = wg_attrs();
     if (e != hipSuccess) return e;
     const int grid = L.item_count < L.max_groups ? L.item_count : L.max_groups;
-    hipLaunchKernelGGL(k_adjoint_wg, dim3(grid), dim3(kWgThreads), sizeof(WgLds), s, L);
+    if (np <= 64)
+        hipLaunchKernelGGL(k_adjoint_wg<true>, dim3(grid), dim3(kWgThreads), sizeof(WgLds), s, L);
+    else
+        hipLaunchKernelGGL(k_adjoint_wg<false>, dim3(grid), dim3(kWgThreads), sizeof(WgLds), s, L);
     return hipGetLastError();
 }
 
