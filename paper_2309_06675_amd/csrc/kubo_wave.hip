@@ -545,6 +545,19 @@ __device__ void wave_backtransform(const WaveLds<NP>& S, int n, double2 (&u)[NP 
     }
 }
 
+// Upper triangle (diagonal included) of an NP x NP matrix packed row by row:
+// row i starts at s(i) = i NP - i (i - 1) / 2.  Element e -> (i, j), i <= j.
+template <int NP>
+__device__ __forceinline__ void upper_index(int e, int& i, int& j) {
+    constexpr float b = 2.0f * NP + 1.0f;
+    int r = (int)(0.5f * (b - sqrtf(b * b - 8.0f * (float)e)));
+    auto start = [](int q) { return q * NP - (q * (q - 1)) / 2; };
+    if (start(r) > e) --r;
+    else if (start(r + 1) <= e) ++r;
+    i = r;
+    j = r + (e - start(r));
+}
+
 // M = U^+ v U for one velocity; lane (i = lane/2, half h) returns row i,
 // columns [h NP/2, (h+1) NP/2) of M in M[].  v_il = sum_rho coef_rho T[rho][i][l],
 // coef = e^{i k0 rho} (times i rho for v_x).  W = v U passes through S.P.
@@ -596,23 +609,25 @@ __device__ void wave_velocity(WaveLds<NP>& S, int n, int nR0, const double2* __r
 
 // v (v_x if is_x, else v_y) into S.P, zero-padded to NP x NP:
 // v_il = sum_rho coef_rho T[rho][i][l], coef = e^{i k0 rho} (times i rho for v_x).
-// Lane-contiguous elements, so the pencil partial sums are read coalesced.
+// v is Hermitian (the hoppings are Hermitian-projected), so only the upper
+// triangle is summed and the lower one is its mirror; consecutive lanes take
+// consecutive elements of a row, so the loads stay coalesced.
 template <int NP>
 __device__ void wave_stage_velocity(WaveLds<NP>& S, int n, int nR0, const double2* __restrict__ T,
                                     const int* __restrict__ r0, bool is_x) {
     constexpr int LD = WaveLds<NP>::LD;
-    constexpr int PER = NP * NP / 64;
+    constexpr int NU = NP * (NP + 1) / 2;
+    constexpr int PER = (NU + 63) / 64;
     const int lane = threadIdx.x & 63;
     const long long nn = (long long)n * n;
     double2 acc[PER];
-    int off[PER];
-    bool valid[PER];
+    int off[PER];  // -1: padding
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         const int e = lane + 64 * q;
-        const int i = e / NP, l = e % NP;
-        valid[q] = (i < n) && (l < n);
-        off[q] = i * n + l;
+        int i, j;
+        upper_index<NP>(e < NU ? e : 0, i, j);
+        off[q] = (e < NU && j < n) ? i * n + j : -1;
         acc[q] = c_make(0.0, 0.0);
     }
     for (int rho = 0; rho < nR0; ++rho) {
@@ -621,12 +636,19 @@ __device__ void wave_stage_velocity(WaveLds<NP>& S, int n, int nR0, const double
         const double2* Tr = T + (long long)rho * nn;
 #pragma unroll
         for (int q = 0; q < PER; ++q)
-            if (valid[q]) acc[q] = c_fma(cf, Tr[off[q]], acc[q]);
+            if (off[q] >= 0) acc[q] = c_fma(cf, Tr[off[q]], acc[q]);
     }
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         const int e = lane + 64 * q;
-        S.P[(e / NP) * LD + (e % NP)] = acc[q];
+        if (e < NU) {
+            int i, j;
+            upper_index<NP>(e, i, j);
+            double2 v = acc[q];
+            if (i == j) v.y = 0.0;
+            S.P[i * LD + j] = v;
+            S.P[j * LD + i] = c_conj(v);
+        }
     }
 }
 
@@ -775,18 +797,19 @@ __device__ bool wave_eigen(WaveLds<NP>& S, const ModelDev& md, const double2* __
     if (lane < md.nR0) S.ph[lane] = unit_phase((long long)i0 * r0[lane], md.N0);
     __syncthreads();
     {
-        // H (upper triangle, mirrored so that it is exactly Hermitian) and v_x
-        // from one pass over the pencil partial sums, all loads of one rho in flight
-        constexpr int PER = NP * NP / 64;
+        // H and v_x from one pass over the upper triangles of the pencil partial
+        // sums (both are Hermitian: the lower triangle is the mirror, so both are
+        // exactly Hermitian), all loads of one rho in flight
+        constexpr int NU = NP * (NP + 1) / 2;
+        constexpr int PER = (NU + 63) / 64;
         double2 acc[PER], accx[PER];
-        int off[PER];
-        bool valid[PER];
+        int off[PER];  // -1: padding
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int e = lane + 64 * q;
-            const int i = e / NP, j = e % NP;
-            valid[q] = (i < n) && (j < n);
-            off[q] = i * n + j;
+            int i, j;
+            upper_index<NP>(e < NU ? e : 0, i, j);
+            off[q] = (e < NU && j < n) ? i * n + j : -1;
             acc[q] = c_make(0.0, 0.0);
             accx[q] = c_make(0.0, 0.0);
         }
@@ -796,7 +819,7 @@ __device__ bool wave_eigen(WaveLds<NP>& S, const ModelDev& md, const double2* __
             const double2* Tr = T0 + (long long)rho * nn;
 #pragma unroll
             for (int q = 0; q < PER; ++q) {
-                if (valid[q]) {
+                if (off[q] >= 0) {
                     const double2 tv = Tr[off[q]];
                     acc[q] = c_fma(tv, ph, acc[q]);
                     accx[q] = c_fma(cf, tv, accx[q]);
@@ -806,14 +829,21 @@ __device__ bool wave_eigen(WaveLds<NP>& S, const ModelDev& md, const double2* __
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int e = lane + 64 * q;
-            const int i = e / NP, j = e % NP;
-            if (valid[q] && i <= j) {
-                double2 h = acc[q];
-                if (i == j) h.y = 0.0;
-                S.P[i * LD + j] = h;
-                S.P[j * LD + i] = c_conj(h);
+            if (e < NU) {
+                int i, j;
+                upper_index<NP>(e, i, j);
+                double2 h = acc[q], x = accx[q];
+                if (i == j) {
+                    h.y = 0.0;
+                    x.y = 0.0;
+                }
+                if (off[q] >= 0) {
+                    S.P[i * LD + j] = h;
+                    S.P[j * LD + i] = c_conj(h);
+                }
+                S.U[i * LD + j] = x;
+                S.U[j * LD + i] = c_conj(x);
             }
-            S.U[i * LD + j] = valid[q] ? accx[q] : c_make(0.0, 0.0);
         }
     }
     vx_in_p = true;
