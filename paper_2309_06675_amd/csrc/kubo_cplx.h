@@ -26,6 +26,14 @@ __device__ __forceinline__ double2 c_fma(double2 a, double2 b, double2 acc) {
     acc.y = fma(a.y, b.x, acc.y);
     return acc;
 }
+// acc - a * b
+__device__ __forceinline__ double2 c_fnma(double2 a, double2 b, double2 acc) {
+    acc.x = fma(-a.x, b.x, acc.x);
+    acc.x = fma(a.y, b.y, acc.x);
+    acc.y = fma(-a.x, b.y, acc.y);
+    acc.y = fma(-a.y, b.x, acc.y);
+    return acc;
+}
 // acc + conj(a) * b
 __device__ __forceinline__ double2 c_fmac(double2 a, double2 b, double2 acc) {
     acc.x = fma(a.x, b.x, acc.x);
@@ -84,6 +92,18 @@ __device__ __forceinline__ double2 c_cmul(double2 a, double2 b) {
 }
 __device__ __forceinline__ double2 c_mulc(double2 a, double2 b) {
     return c_make(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+// acc - a conj(b) - c conj(d) (a Hermitian rank-2 update) as eight chained FMAs
+__device__ __forceinline__ double2 c_rank2c(double2 acc, double2 a, double2 b, double2 c, double2 d) {
+    acc.x = fma(-a.x, b.x, acc.x);
+    acc.x = fma(-a.y, b.y, acc.x);
+    acc.x = fma(-c.x, d.x, acc.x);
+    acc.x = fma(-c.y, d.y, acc.x);
+    acc.y = fma(-a.y, b.x, acc.y);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(-c.y, d.x, acc.y);
+    acc.y = fma(c.x, d.y, acc.y);
+    return acc;
 }
 
 // Work-item schedule of the persistent per-k kernels.  Workgroups are handed to

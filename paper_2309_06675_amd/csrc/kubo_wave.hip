@@ -231,7 +231,7 @@ __device__ void wave_tridiag(WaveLds<NP>& S, int n, double& d_lane, double& e_la
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     const int jj = 4 * gq + t;
-                    a[jj] = c_sub(a[jj], c_add(c_mulc(v, wc[t]), c_mulc(w, vc[jj])));
+                    a[jj] = c_rank2c(a[jj], v, wc[t], w, vc[jj]);
                 }
             }
         }
@@ -540,7 +540,7 @@ __device__ void wave_backtransform(const WaveLds<NP>& S, int n, double2 (&u)[NP 
         for (int gq = 0; gq < HW / 4; ++gq)
             if (8 * gq + 7 > k) {
 #pragma unroll
-                for (int t = 0; t < 4; ++t) u[4 * gq + t] = c_sub(u[4 * gq + t], c_mul(vr[4 * gq + t], ty));
+                for (int t = 0; t < 4; ++t) u[4 * gq + t] = c_fnma(vr[4 * gq + t], ty, u[4 * gq + t]);
             }
     }
 }
@@ -1367,7 +1367,7 @@ __global__ __launch_bounds__(64) void k_adjoint_wave(WgLaunch a) {
                                     const double den = x * x + eta2;
                                     const double w = dphx / den - (phx - S.phi[p]) * 2.0 * x / (den * den);
                                     double2 z = c_mul(S.U[m * LD + p], S.P[p * LD + c]);
-                                    z = c_sub(z, c_mul(S.P[m * LD + p], S.U[p * LD + c]));
+                                    z = c_fnma(S.P[m * LD + p], S.U[p * LD + c], z);
                                     acc = c_add(acc, c_scale(w, z));
                                 }
                                 acc = c_scale(invN, c_i(acc));

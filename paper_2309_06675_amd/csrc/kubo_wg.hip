@@ -185,7 +185,7 @@ __device__ void wg_tridiag(WgLds& S, double2* __restrict__ P, int n) {
         for (int e = tid; e < m * m; e += kWgThreads) {
             const int r = k + 1 + e / m, c = k + 1 + (e - (e / m) * m);
             double2 a = P[r * n + c];
-            a = c_sub(a, c_add(c_mulc(S.vv[r], S.wv[c]), c_mulc(S.wv[r], S.vv[c])));
+            a = c_rank2c(a, S.vv[r], S.wv[c], S.wv[r], S.vv[c]);
             P[r * n + c] = a;
         }
         __syncthreads();
@@ -466,7 +466,7 @@ __device__ void wg_backtransform_reg(WgLds& S, const double2* __restrict__ P, do
 #pragma unroll
                     for (int t = 0; t < 4; ++t) {
                         const int jj = 4 * gq + t;
-                        u[jj] = c_sub(u[jj], c_mul(v[G * jj + g], ty));
+                        u[jj] = c_fnma(v[G * jj + g], ty, u[jj]);
                     }
                 }
             }
@@ -502,7 +502,7 @@ __device__ void wg_backtransform(WgLds& S, const double2* __restrict__ P, double
         }
         const double2 ty = c_mul(tau, y);
         if (act)
-            for (int r = k + 1 + g; r < n; r += G) U[r * n + c] = c_sub(U[r * n + c], c_mul(S.vv[r], ty));
+            for (int r = k + 1 + g; r < n; r += G) U[r * n + c] = c_fnma(S.vv[r], ty, U[r * n + c]);
         __syncthreads();
     }
     __syncthreads();
@@ -722,7 +722,7 @@ __global__ __launch_bounds__(kWgThreads, SMALL ? 2 : 1) void k_adjoint_wg(WgLaun
                     for (int p = 0; p < n; ++p) {
                         const double w = X.K[m * n + p] - X.K[q * n + p];
                         double2 z = c_mul(B[m * n + p], A[p * n + q]);
-                        z = c_sub(z, c_mul(A[m * n + p], B[p * n + q]));
+                        z = c_fnma(A[m * n + p], B[p * n + q], z);
                         acc = c_add(acc, c_scale(w, z));
                     }
                     acc = c_scale(invN / de, c_i(acc));
@@ -740,7 +740,7 @@ __global__ __launch_bounds__(kWgThreads, SMALL ? 2 : 1) void k_adjoint_wg(WgLaun
                         const double den = x * x + eta2;
                         const double w = dphx / den - (phx - S.phi[p]) * 2.0 * x / (den * den);
                         double2 z = c_mul(B[m * n + p], A[p * n + q]);
-                        z = c_sub(z, c_mul(A[m * n + p], B[p * n + q]));
+                        z = c_fnma(A[m * n + p], B[p * n + q], z);
                         acc = c_add(acc, c_scale(w, z));
                     }
                     acc = c_scale(invN, c_i(acc));
