@@ -351,22 +351,34 @@ __device__ bool wave_ql(WaveLds<NP>& S, int n, double& d_lane, double& e_lane, i
     return ok;
 }
 
-// Eigenvalues of the real symmetric tridiagonal (d, e) in S.de2 by Sturm-count
-// multisection.  Lanes 2j and 2j+1 search eigenvalue j (ascending): each step
-// they count at 2 NS interior points of [lo, hi] (NS interleaved Sturm
-// sequences per lane) and keep the sub-interval that holds eigenvalue j.
-// With the tridiagonal matrix in registers the recurrence is issue bound, so
-// the total count of sequence steps (NS times the number of steps) decides:
-// NS = 1 (trisection) measured fastest, ahead of 2 and 3.
-// A fixed number of steps shrinks the Gershgorin interval below 4 eps max|lambda|.
-// Returns lambda_j in both lanes.
+// Eigenvalues of the real symmetric tridiagonal matrix (d, e) in S.de2, lanes
+// 2j and 2j+1 both returning eigenvalue j (ascending).  Each pass evaluates the
+// Sturm sequence q_i = (d_i - x) - e_{i-1}^2 / q_{i-1} at one point per lane:
+// the number of negative q_i is the number of eigenvalues below x, and, when
+// asked for, the same recurrence gives S = d/dx log|det(T - x I)| = sum q_i'/q_i
+// with q_i' = -1 + e_{i-1}^2 q_{i-1}' / q_{i-1}^2, so x - 1/S is the Newton step
+// on det(T - x I).  Every lane pair keeps a bracket lo <= lambda_j < hi with
+// the counts at its ends and, per pass:
+//  * while lambda_j is not the only eigenvalue in the bracket: trisection (the
+//    two lanes take the points at one and two thirds);
+//  * once it is: lane 0 takes the Newton point of the previous pass, lane 1 the
+//    bracket's midpoint (so the bracket at least halves every pass);
+//  * a Newton step below the tolerance 4 eps max|lambda| is accepted only after
+//    a verifying pass finds lambda_j between c - 2 tol and c + 2 tol by counts.
+// The counts decide everything, as in plain bisection, so a poor derivative
+// (cancellation near an eigenvalue of a leading submatrix) can cost passes but
+// not accuracy.  Well-separated spectra finish in about a third of the passes of
+// trisection to the same tolerance; clustered ones fall back to trisection.
 template <int NP>
 __device__ double wave_bisect(const WaveLds<NP>& S, int n, double glo, double ghi, double pivmin) {
-    constexpr int NS = 1;  // points per lane
-    constexpr double inv_sections = 1.0 / (2 * NS + 1);
+    constexpr int kMaxPasses = 96;
     const int lane = threadIdx.x & 63;
     const int j = lane >> 1;
     const int half = lane & 1;
+    auto rcp = [](double q) {
+        const double r = __builtin_amdgcn_rcp(q);
+        return fma(r, fma(-q, r, 1.0), r);
+    };
     // the matrix in registers; rows past n decouple (e = 0) and never count (d huge)
     double dv[NP], e2v[NP];
 #pragma unroll
@@ -375,54 +387,94 @@ __device__ double wave_bisect(const WaveLds<NP>& S, int n, double glo, double gh
         dv[i] = (i < n) ? de.x : 1e300;
         e2v[i] = (i < n) ? de.y * de.y : 0.0;
     }
-    double lo = glo, hi = ghi;
     const double scale = fmax(fabs(glo), fabs(ghi));
     const double tol = 4.0 * 2.220446049250313e-16 * scale + 1e-300;
-    int steps = 0;
-    for (double w = ghi - glo; w > tol && steps < 60; w *= inv_sections) ++steps;
-    for (int it = 0; it < steps; ++it) {
-        const double step = (hi - lo) * inv_sections;
-        double x[NS], q[NS];
-        int cnt[NS];
+    double lo = glo, hi = ghi, cand = 0.0, lam = ghi;
+    int clo = 0, chi = n;
+    bool done = j >= n, has = false, ver = false;
+    for (int pass = 0; pass < kMaxPasses; ++pass) {
+        if (__ballot(!done) == 0ull) break;
+        const bool iso = (clo == j) && (chi == j + 1);
+        const double w = hi - lo;
+        double x;
+        if (ver)
+            x = half ? cand + 2.0 * tol : cand - 2.0 * tol;
+        else if (iso && has)
+            x = half ? lo + 0.5 * w : cand;
+        else
+            x = lo + (double)(half + 1) * (w * (1.0 / 3.0));
+        const bool need_d = __ballot(!done && iso && !ver) != 0ull;  // wave-uniform
+        int cnt = 0;
+        double sd = 0.0;
+        if (need_d) {
+            double q = 1.0, qd = 0.0;
 #pragma unroll
-        for (int t = 0; t < NS; ++t) {
-            x[t] = lo + (double)(half * NS + t + 1) * step;
-            q[t] = 1.0;
-            cnt[t] = 0;
-        }
-#pragma unroll
-        for (int i = 0; i < NP; ++i) {
-            const double e2p = (i > 0) ? e2v[i - 1] : 0.0;
-#pragma unroll
-            for (int t = 0; t < NS; ++t) {
-                // reciprocal estimate refined by one Newton step (full FP64 precision)
-                double rq = __builtin_amdgcn_rcp(q[t]);
-                rq = fma(rq, fma(-q[t], rq, 1.0), rq);
-                double qi = fma(-e2p, rq, dv[i] - x[t]);
+            for (int i = 0; i < NP; ++i) {
+                const double e2p = (i > 0) ? e2v[i - 1] : 0.0;
+                const double rq = rcp(q);
+                sd = fma(qd, rq, sd);  // q'_{i-1} / q_{i-1}
+                const double t = e2p * rq;
+                double qi = (dv[i] - x) - t;
                 if (fabs(qi) < pivmin) qi = -pivmin;
-                cnt[t] += (qi < 0.0) ? 1 : 0;
-                q[t] = qi;
+                qd = fma(t * rq, qd, -1.0);
+                cnt += (qi < 0.0) ? 1 : 0;
+                q = qi;
+            }
+            sd = fma(qd, rcp(q), sd);
+        } else {
+            double q = 1.0;
+#pragma unroll
+            for (int i = 0; i < NP; ++i) {
+                const double e2p = (i > 0) ? e2v[i - 1] : 0.0;
+                double qi = fma(-e2p, rcp(q), dv[i] - x);
+                if (fabs(qi) < pivmin) qi = -pivmin;
+                cnt += (qi < 0.0) ? 1 : 0;
+                q = qi;
             }
         }
-        // counts at the 2 NS points, ascending: this lane's and its partner's
-        int c[2 * NS];
-#pragma unroll
-        for (int t = 0; t < NS; ++t) {
-            const int other = __builtin_amdgcn_update_dpp(0, cnt[t], 0xB1, 0xF, 0xF, false);
-            c[t] = half ? other : cnt[t];
-            c[NS + t] = half ? cnt[t] : other;
+        // both lanes of the pair see both points in the same order
+        const double xo = dpp_xor1(x), so = dpp_xor1(sd);
+        const int co = __builtin_amdgcn_update_dpp(0, cnt, 0xB1, 0xF, 0xF, false);
+        const double x0 = half ? xo : x, x1 = half ? x : xo;
+        const double s0 = half ? so : sd, s1 = half ? sd : so;
+        const int c0 = half ? co : cnt, c1 = half ? cnt : co;
+        if (done) continue;
+        if (ver && c0 <= j && c1 > j) {  // lambda_j within 2 tol of the Newton value
+            done = true;
+            lam = cand;
+            continue;
         }
-        // eigenvalue j lies in [x_m, x_{m+1}) for the first point m+1 whose count exceeds j
-        int m = 2 * NS;
-#pragma unroll
-        for (int t = 2 * NS - 1; t >= 0; --t)
-            if (c[t] > j) m = t;
-        const double nlo = (m == 0) ? lo : lo + (double)m * step;
-        const double nhi = (m == 2 * NS) ? hi : lo + (double)(m + 1) * step;
-        lo = nlo;
-        hi = nhi;
+        if (c0 <= j && x0 > lo) { lo = x0; clo = c0; }
+        if (c1 <= j && x1 > lo) { lo = x1; clo = c1; }
+        if (c0 > j && x0 < hi) { hi = x0; chi = c0; }
+        if (c1 > j && x1 < hi) { hi = x1; chi = c1; }
+        const bool was_ver = ver;
+        ver = false;
+        has = false;
+        if (need_d && !was_ver) {
+            // Newton points from both evaluations; keep the shorter step in the bracket
+            const double na = x0 - 1.0 / s0, nb = x1 - 1.0 / s1;
+            const bool ina = (na >= lo - tol) && (na <= hi + tol);
+            const bool inb = (nb >= lo - tol) && (nb <= hi + tol);
+            const double sta = fabs(na - x0), stb = fabs(nb - x1);
+            const bool pb = inb && (!ina || stb < sta);
+            if (ina || inb) {
+                const double c = pb ? nb : na;
+                const double st = pb ? stb : sta;
+                cand = fmin(fmax(c, lo), hi);
+                if ((clo == j) && (chi == j + 1) && st <= tol)
+                    ver = true;
+                else
+                    has = (c > lo) && (c < hi);
+            }
+        }
+        if (!ver && hi - lo <= tol) {
+            done = true;
+            lam = 0.5 * (lo + hi);
+        }
     }
-    return 0.5 * (lo + hi);
+    if (!done) lam = 0.5 * (lo + hi);
+    return lam;
 }
 
 // Eigenvector of the tridiagonal matrix for an isolated eigenvalue lam by the
