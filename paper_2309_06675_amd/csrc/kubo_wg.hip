@@ -107,22 +107,35 @@ __device__ void wg_build(WgLds& S, const WgScratch& X, const ModelDev& md,
     const long long nn = (long long)n * n;
     if (threadIdx.x < md.nR0) S.ph[threadIdx.x] = unit_phase((long long)i0 * r0[threadIdx.x], md.N0);
     __syncthreads();
-    for (int e = threadIdx.x; e < n * n; e += kWgThreads) {
-        const int i = e / n, j = e - (e / n) * n;
+    // H, v_x and v_y are Hermitian (the hoppings are Hermitian-projected): the
+    // upper triangles are summed, packed row by row, and mirrored
+    const int nu = n * (n + 1) / 2;
+    for (int e = threadIdx.x; e < nu; e += kWgThreads) {
+        // row i starts at s(i) = i n - i (i - 1) / 2
+        const float b = 2.0f * n + 1.0f;
+        int i = (int)(0.5f * (b - sqrtf(b * b - 8.0f * (float)e)));
+        if (i * n - (i * (i - 1)) / 2 > e) --i;
+        else if ((i + 1) * n - ((i + 1) * i) / 2 <= e) ++i;
+        const int j = i + (e - (i * n - (i * (i - 1)) / 2));
+        const long long off = (long long)i * n + j;
         double2 h = c_make(0.0, 0.0), x = h, y = h;
         for (int rho = 0; rho < md.nR0; ++rho) {
-            const double2 p0 = c_mul(T0[(long long)rho * nn + e], S.ph[rho]);
+            const double2 p0 = c_mul(T0[(long long)rho * nn + off], S.ph[rho]);
             h = c_add(h, p0);
             x = c_add(x, c_scale((double)r0[rho], c_i(p0)));
-            y = c_fma(T1[(long long)rho * nn + e], S.ph[rho], y);
+            y = c_fma(T1[(long long)rho * nn + off], S.ph[rho], y);
         }
-        X.VX[e] = x;
-        X.VY[e] = y;
-        if (i <= j) {
-            if (i == j) h.y = 0.0;
-            X.P[i * n + j] = h;
-            X.P[j * n + i] = c_conj(h);
+        if (i == j) {
+            h.y = 0.0;
+            x.y = 0.0;
+            y.y = 0.0;
         }
+        X.P[i * n + j] = h;
+        X.P[j * n + i] = c_conj(h);
+        X.VX[i * n + j] = x;
+        X.VX[j * n + i] = c_conj(x);
+        X.VY[i * n + j] = y;
+        X.VY[j * n + i] = c_conj(y);
     }
     __syncthreads();
 }
@@ -198,7 +211,16 @@ __device__ void wg_tridiag(WgLds& S, double2* __restrict__ P, int n) {
 }
 
 // ---------------------------------------------------------------------------
-// step 2b: eigenvalues by Sturm-count multisection (S.lam ascending)
+// step 2b: eigenvalues (S.lam ascending) by Sturm counts with safeguarded
+// Newton steps: tpe threads per eigenvalue keep one bracket lo <= lambda_j < hi
+// (with the counts at its ends).  Per pass, while lambda_j is not alone in the
+// bracket the threads count at tpe equally spaced interior points
+// (multisection); once it is, thread 0 takes the Newton point x - 1/S of the
+// previous pass, S = d/dx log|det(T - x I)| from the derivative recurrence
+// q_i' = -1 + e_{i-1}^2 q_{i-1}' / q_{i-1}^2, and the others split the bracket.
+// A Newton step below the tolerance is accepted only after a pass whose counts
+// at c -/+ 2 tol bracket lambda_j, so the counts decide the result as in
+// bisection.
 // ---------------------------------------------------------------------------
 __device__ void wg_bisect(WgLds& S, int n, double& pivmin_out, double& span_out) {
     const int tid = threadIdx.x;
@@ -215,40 +237,114 @@ __device__ void wg_bisect(WgLds& S, int n, double& pivmin_out, double& span_out)
     const double pivmin = 1e-290 * fmax(1.0, em * em);
     pivmin_out = pivmin;
     span_out = fmax(fabs(glo), fabs(ghi));
+    auto rcp = [](double q) {
+        const double r = __builtin_amdgcn_rcp(q);
+        return fma(r, fma(-q, r, 1.0), r);
+    };
     int np2 = 1;
     while (np2 < n) np2 <<= 1;
-    const int tpe = kWgThreads / np2;  // threads per eigenvalue (>= 2)
+    const int tpe = kWgThreads / np2;  // threads per eigenvalue (>= 2, divides 64)
     const int j = tid / tpe, q = tid - (tid / tpe) * tpe;
+    const int base = (tid & 63) - q;  // first lane of the group
     const double tol = 4.0 * 2.220446049250313e-16 * span_out + 1e-300;
-    int steps = 0;
-    for (double w = ghi - glo; w > tol && steps < 120; w /= (double)(tpe + 1)) ++steps;
-    double lo = glo, hi = ghi;
-    for (int it = 0; it < steps; ++it) {
-        const double h = (hi - lo) / (double)(tpe + 1);
-        const double x = lo + h * (double)(q + 1);
+    double lo = glo, hi = ghi, cand = 0.0, lam = ghi;
+    int clo = 0, chi = n;
+    bool done = j >= n, has = false, ver = false;
+    for (int pass = 0; pass < 160; ++pass) {
+        if (__ballot(!done) == 0ull) break;  // per wavefront: whole groups
+        const bool iso = (clo == j) && (chi == j + 1);
+        const double w = hi - lo;
+        double x;
+        if (ver)
+            x = (q == 0) ? cand - 2.0 * tol : ((q == 1) ? cand + 2.0 * tol : lo + w * (double)q / (double)tpe);
+        else if (iso && has)
+            x = (q == 0) ? cand : lo + w * (double)q / (double)tpe;
+        else
+            x = lo + w * (double)(q + 1) / (double)(tpe + 1);
+        const bool need_d = __ballot(!done && iso && !ver) != 0ull;
         int cnt = 0;
-        double qv = 1.0, e2prev = 0.0;
-        for (int i = 0; i < n; ++i) {
-            double rq = __builtin_amdgcn_rcp(qv);
-            rq = fma(rq, fma(-qv, rq, 1.0), rq);
-            double qi = (S.d[i] - x) - e2prev * rq;
-            if (fabs(qi) < pivmin) qi = -pivmin;
-            cnt += (qi < 0.0) ? 1 : 0;
-            qv = qi;
-            e2prev = S.e[i] * S.e[i];
+        double sd = 0.0;
+        if (need_d) {
+            double qv = 1.0, qd = 0.0, e2prev = 0.0;
+            for (int i = 0; i < n; ++i) {
+                const double rq = rcp(qv);
+                sd = fma(qd, rq, sd);  // q'_{i-1} / q_{i-1}
+                const double t = e2prev * rq;
+                double qi = (S.d[i] - x) - t;
+                if (fabs(qi) < pivmin) qi = -pivmin;
+                qd = fma(t * rq, qd, -1.0);
+                cnt += (qi < 0.0) ? 1 : 0;
+                qv = qi;
+                e2prev = S.e[i] * S.e[i];
+            }
+            sd = fma(qd, rcp(qv), sd);
+        } else {
+            double qv = 1.0, e2prev = 0.0;
+            for (int i = 0; i < n; ++i) {
+                double qi = fma(-e2prev, rcp(qv), S.d[i] - x);
+                if (fabs(qi) < pivmin) qi = -pivmin;
+                cnt += (qi < 0.0) ? 1 : 0;
+                qv = qi;
+                e2prev = S.e[i] * S.e[i];
+            }
         }
-        // first point whose count exceeds j decides the new interval
-        int first = tpe;  // index of the first point with count > j
+        // this thread's Newton point
+        const double nx = need_d ? x - 1.0 / sd : 0.0;
+        const double nst = fabs(nx - x);
+        // every thread of the group applies all tpe points in the same order
+        const int c0 = __shfl(cnt, base, 64), c1 = __shfl(cnt, base + 1, 64);
+        const bool verified = ver && c0 <= j && c1 > j;
         for (int p = 0; p < tpe; ++p) {
-            const int cp = __shfl(cnt, (tid & 63) - q + p, 64);
-            if (cp > j && first == tpe) first = p;
+            const double xp = __shfl(x, base + p, 64);
+            const int cp = __shfl(cnt, base + p, 64);
+            if (!done && !verified) {
+                if (cp <= j && xp > lo) {
+                    lo = xp;
+                    clo = cp;
+                }
+                if (cp > j && xp < hi) {
+                    hi = xp;
+                    chi = cp;
+                }
+            }
         }
-        const double nlo = lo + h * (double)first;
-        const double nhi = (first == tpe) ? hi : lo + h * (double)(first + 1);
-        lo = nlo;
-        hi = nhi;
+        bool found = false;
+        double best = 0.0, bst = 0.0;
+        if (need_d) {
+            for (int p = 0; p < tpe; ++p) {
+                const double np_ = __shfl(nx, base + p, 64);
+                const double sp = __shfl(nst, base + p, 64);
+                const bool in = (np_ >= lo - tol) && (np_ <= hi + tol);
+                if (in && (!found || sp < bst)) {
+                    found = true;
+                    best = np_;
+                    bst = sp;
+                }
+            }
+        }
+        if (done) continue;
+        if (verified) {
+            done = true;
+            lam = cand;
+            continue;
+        }
+        const bool was_ver = ver;
+        ver = false;
+        has = false;
+        if (found && !was_ver) {
+            cand = fmin(fmax(best, lo), hi);
+            if ((clo == j) && (chi == j + 1) && bst <= tol)
+                ver = true;
+            else
+                has = (best > lo) && (best < hi);
+        }
+        if (!ver && hi - lo <= tol) {
+            done = true;
+            lam = 0.5 * (lo + hi);
+        }
     }
-    if (q == 0 && j < n) S.lam[j] = 0.5 * (lo + hi);
+    if (!done) lam = 0.5 * (lo + hi);
+    if (q == 0 && j < n) S.lam[j] = lam;
     __syncthreads();
 }
 
