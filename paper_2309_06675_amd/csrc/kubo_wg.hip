@@ -604,47 +604,66 @@ __device__ void wg_backtransform(WgLds& S, const double2* __restrict__ P, double
     __syncthreads();
 }
 
-// ---------------------------------------------------------------------------
-// C = LA * LB through 32 x 32 LDS tiles; LA(i, k) and LB(k, j) return the
-// operand elements (so transposes, conjugates and elementwise factors are free)
-// ---------------------------------------------------------------------------
+// C = A B (n x n, complex) on the FP64 matrix cores; A and B come from the
+// element functions LA(i, k), LB(k, j) (global scratch, transposes and
+// conjugates folded in), C must not alias them.  The four wavefronts take
+// 32 x 32 blocks of C in turn; a block is 2 x 2 tiles of v_mfma_f64_16x16x4
+// with separate real and imaginary accumulators (four real products per
+// complex one).  Lane (g, c) = (lane / 16, lane % 16) supplies A[16 t + c][k]
+// and B[k][16 t + c] for k = 4 kk + g; elements past n are zero.
+typedef double wg_v4d __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ wg_v4d wg_mfma16(double a, double b, wg_v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
 template <class FA, class FB>
 __device__ void wg_gemm(WgLds& S, double2* __restrict__ C, int n, FA LA, FB LB) {
-    const int tid = threadIdx.x;
-    const int ti = tid >> 4, tj = tid & 15;  // 2 x 2 outputs per thread
-    const int nt = (n + kTile - 1) / kTile;
-    for (int bi = 0; bi < nt; ++bi)
-        for (int bj = 0; bj < nt; ++bj) {
-            double2 acc[2][2];
-            for (int a = 0; a < 2; ++a)
-                for (int b = 0; b < 2; ++b) acc[a][b] = c_make(0.0, 0.0);
-            for (int bk = 0; bk < nt; ++bk) {
-                for (int e = tid; e < kTile * kTile; e += kWgThreads) {
-                    const int r = e / kTile, c = e - (e / kTile) * kTile;
-                    const int gi = bi * kTile + r, gk = bk * kTile + c;
-                    S.ta[r * (kTile + 1) + c] = (gi < n && gk < n) ? LA(gi, gk) : c_make(0.0, 0.0);
-                    const int gk2 = bk * kTile + r, gj = bj * kTile + c;
-                    S.tb[r * (kTile + 1) + c] = (gk2 < n && gj < n) ? LB(gk2, gj) : c_make(0.0, 0.0);
-                }
-                __syncthreads();
-                for (int kk = 0; kk < kTile; ++kk) {
-                    const double2 a0 = S.ta[(2 * ti) * (kTile + 1) + kk];
-                    const double2 a1 = S.ta[(2 * ti + 1) * (kTile + 1) + kk];
-                    const double2 b0 = S.tb[kk * (kTile + 1) + 2 * tj];
-                    const double2 b1 = S.tb[kk * (kTile + 1) + 2 * tj + 1];
-                    acc[0][0] = c_fma(a0, b0, acc[0][0]);
-                    acc[0][1] = c_fma(a0, b1, acc[0][1]);
-                    acc[1][0] = c_fma(a1, b0, acc[1][0]);
-                    acc[1][1] = c_fma(a1, b1, acc[1][1]);
-                }
-                __syncthreads();
+    (void)S;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int g = lane >> 4, c = lane & 15;
+    const int nb = (n + 31) >> 5;  // 32 x 32 blocks per dimension
+    const int nk = (n + 3) >> 2;   // k-steps of four
+    const wg_v4d zero = {0.0, 0.0, 0.0, 0.0};
+    for (int blk = wv; blk < nb * nb; blk += kWgThreads / 64) {
+        const int bi = blk / nb, bj = blk - (blk / nb) * nb;
+        wg_v4d cr[2][2], ci[2][2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                cr[a][b] = zero;
+                ci[a][b] = zero;
             }
-            for (int a = 0; a < 2; ++a)
-                for (int b = 0; b < 2; ++b) {
-                    const int gi = bi * kTile + 2 * ti + a, gj = bj * kTile + 2 * tj + b;
-                    if (gi < n && gj < n) C[gi * n + gj] = acc[a][b];
+#pragma unroll 2
+        for (int kk = 0; kk < nk; ++kk) {
+            const int k = 4 * kk + g;
+            double2 av[2], bv[2];
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const int row = 32 * bi + 16 * t + c, col = 32 * bj + 16 * t + c;
+                av[t] = (row < n && k < n) ? LA(row, k) : c_make(0.0, 0.0);
+                bv[t] = (k < n && col < n) ? LB(k, col) : c_make(0.0, 0.0);
+            }
+#pragma unroll
+            for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < 2; ++tj) {
+                    cr[ti][tj] = wg_mfma16(av[ti].x, bv[tj].x, cr[ti][tj]);
+                    cr[ti][tj] = wg_mfma16(-av[ti].y, bv[tj].y, cr[ti][tj]);
+                    ci[ti][tj] = wg_mfma16(av[ti].x, bv[tj].y, ci[ti][tj]);
+                    ci[ti][tj] = wg_mfma16(av[ti].y, bv[tj].x, ci[ti][tj]);
                 }
         }
+#pragma unroll
+        for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+            for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int row = 32 * bi + 16 * ti + g + 4 * q, col = 32 * bj + 16 * tj + c;
+                    if (row < n && col < n) C[row * n + col] = c_make(cr[ti][tj][q], ci[ti][tj][q]);
+                }
+    }
     __syncthreads();
 }
 
@@ -695,9 +714,9 @@ __device__ bool wg_eigen_velocities(WgLds& S, const WgScratch& X, const ModelDev
 // ---------------------------------------------------------------------------
 // k_forward_wg
 // ---------------------------------------------------------------------------
-// SMALL (n <= 64): register back-transformation, two waves per SIMD
+// SMALL (n <= 64): register back-transformation; both instantiations run two waves per SIMD
 template <bool SMALL>
-__global__ __launch_bounds__(kWgThreads, SMALL ? 2 : 1) void k_forward_wg(WgLaunch a) {
+__global__ __launch_bounds__(kWgThreads, 2) void k_forward_wg(WgLaunch a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     WgLds& S = *reinterpret_cast<WgLds*>(smem_raw);
     const double eta2 = a.eta * a.eta;
@@ -764,7 +783,7 @@ __device__ __forceinline__ void wg_phi_at(double x, const double* __restrict__ e
 // kubo_device.hip for the formulas); writes the block's pencil partials.
 // ---------------------------------------------------------------------------
 template <bool SMALL>
-__global__ __launch_bounds__(kWgThreads, SMALL ? 2 : 1) void k_adjoint_wg(WgLaunch a) {
+__global__ __launch_bounds__(kWgThreads, 2) void k_adjoint_wg(WgLaunch a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     WgLds& S = *reinterpret_cast<WgLds*>(smem_raw);
     const double eta2 = a.eta * a.eta;
