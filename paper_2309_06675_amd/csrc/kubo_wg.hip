@@ -70,10 +70,36 @@ __device__ __forceinline__ WgScratch wg_scratch(double2* base, long long slot_el
     return s;
 }
 
+// Wavefront reduction without the LDS crossbar: DPP within rows of 16 lanes,
+// then the gfx950 row swaps (v_permlane16_swap, v_permlane32_swap); every lane
+// ends with the same bits.
+template <class Op>
+__device__ __forceinline__ double wg_wave_reduce(double v, Op op) {
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));   // lane ^ 1
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));   // lane ^ 2
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false));  // 7 - lane within 8
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false));  // 15 - lane within 16
+    auto join = [](unsigned lo, unsigned hi) {
+        return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+    };
+    {
+        const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+        const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)b, (unsigned)b, false, false);
+        const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+        v = op(join(lo[0], hi[0]), join(lo[1], hi[1]));
+    }
+    {
+        const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+        const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)b, (unsigned)b, false, false);
+        const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+        v = op(join(lo[0], hi[0]), join(lo[1], hi[1]));
+    }
+    return v;
+}
+
 // Workgroup sum of one double (all threads get the result).
 __device__ __forceinline__ double wg_sum(double v, double* red) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    v = wg_wave_reduce(v, [](double x, double y) { return x + y; });
     __syncthreads();
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
@@ -83,8 +109,7 @@ __device__ __forceinline__ double wg_sum(double v, double* red) {
     return s;
 }
 __device__ __forceinline__ double wg_min(double v, double* red) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+    v = wg_wave_reduce(v, [](double x, double y) { return fmin(x, y); });
     __syncthreads();
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
@@ -200,6 +225,106 @@ __device__ void wg_tridiag(WgLds& S, double2* __restrict__ P, int n) {
             double2 a = P[r * n + c];
             a = c_rank2c(a, S.vv[r], S.wv[c], S.wv[r], S.vv[c]);
             P[r * n + c] = a;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        S.d[n - 1] = P[(n - 1) * n + (n - 1)].x;
+        S.e[n - 1] = 0.0;
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// step 2a for n <= 64, the same reduction restructured (measured faster there;
+// wg_tridiag stays faster at n = 128).  Per step: column k through LDS; p = A22 v in column form (A22 is Hermitian,
+// p_r = sum_c conj(A_cr) v_c), each wavefront summing every fourth c with
+// lanes over r (coalesced reads of the scratch rows), the four partial sums
+// combined through LDS (S.ta); the rank-2 update with wavefronts over rows and
+// lanes over columns.  Six barriers per step.
+// ---------------------------------------------------------------------------
+// workgroup sum with one barrier; red[base .. base+3] must not be reused
+// before the next barrier
+__device__ __forceinline__ double wg_sum1(double v, double* red, int base) {
+    v = wg_wave_reduce(v, [](double x, double y) { return x + y; });
+    if ((threadIdx.x & 63) == 0) red[base + (threadIdx.x >> 6)] = v;
+    __syncthreads();
+    return (red[base] + red[base + 1]) + (red[base + 2] + red[base + 3]);
+}
+
+__device__ void wg_tridiag_cols(WgLds& S, double2* __restrict__ P, int n) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    constexpr int NW = kWgThreads / 64;
+    double2* part = S.ta;  // [NW][kWgMaxN] partial sums of p
+    auto rcp = [](double x) {
+        const double r = __builtin_amdgcn_rcp(x);
+        return fma(r, fma(-x, r, 1.0), r);
+    };
+    for (int k = 0; k < n - 1; ++k) {
+        double nrm_part = 0.0;
+        for (int r = k + 1 + tid; r < n; r += kWgThreads) {
+            const double2 x = P[r * n + k];
+            S.xv[r] = x;
+            if (r > k + 1) nrm_part = fma(x.x, x.x, fma(x.y, x.y, nrm_part));
+        }
+        const double xn2 = wg_sum1(nrm_part, S.red, 0);
+        const double2 alpha = S.xv[k + 1];
+        double beta;
+        double2 tau, scal;
+        if (xn2 == 0.0 && alpha.y == 0.0) {
+            beta = alpha.x;
+            tau = c_make(0.0, 0.0);
+            scal = c_make(0.0, 0.0);
+        } else {
+            const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn2);
+            beta = -copysign(nrm, alpha.x);
+            const double ib = rcp(beta);
+            tau = c_make((beta - alpha.x) * ib, -alpha.y * ib);
+            const double ar = alpha.x - beta, ai = alpha.y;
+            const double den = rcp(ar * ar + ai * ai);
+            scal = c_make(ar * den, -ai * den);
+        }
+        if (tid == 0) {
+            S.d[k] = P[k * n + k].x;
+            S.e[k] = beta;
+            S.tau[k] = tau;
+        }
+        for (int r = k + 1 + tid; r < n; r += kWgThreads) {
+            const double2 v = (r == k + 1) ? c_make(1.0, 0.0) : c_mul(S.xv[r], scal);
+            S.vv[r] = v;
+            P[r * n + k] = v;
+        }
+        __syncthreads();
+        if (tau.x == 0.0 && tau.y == 0.0) continue;
+        // partial p_r over c = k + 1 + w (mod NW), two interleaved accumulators
+        for (int r = k + 1 + lane; r < n; r += 64) {
+            double2 a0 = c_make(0.0, 0.0), a1 = a0;
+            int c = k + 1 + w;
+            for (; c + NW < n; c += 2 * NW) {
+                a0 = c_fmac(P[c * n + r], S.vv[c], a0);
+                a1 = c_fmac(P[(c + NW) * n + r], S.vv[c + NW], a1);
+            }
+            if (c < n) a0 = c_fmac(P[c * n + r], S.vv[c], a0);
+            part[w * kWgMaxN + r] = c_add(a0, a1);
+        }
+        __syncthreads();
+        double2 p = c_make(0.0, 0.0), v = p;
+        double mpart = 0.0;
+        const int r = k + 1 + tid;
+        if (r < n) {
+            p = c_add(c_add(part[r], part[kWgMaxN + r]), c_add(part[2 * kWgMaxN + r], part[3 * kWgMaxN + r]));
+            v = S.vv[r];
+            mpart = v.x * p.x + v.y * p.y;
+        }
+        const double mu = wg_sum1(mpart, S.red, NW);  // v^+ p (real)
+        const double t2 = 0.5 * (tau.x * tau.x + tau.y * tau.y) * mu;
+        if (r < n) S.wv[r] = c_sub(c_mul(tau, p), c_scale(t2, v));
+        __syncthreads();
+        // A22 <- A22 - v w^+ - w v^+: wavefronts over rows, lanes over columns
+        for (int rr = k + 1 + w; rr < n; rr += NW) {
+            const double2 vr = S.vv[rr], wr = S.wv[rr];
+            for (int c = k + 1 + lane; c < n; c += 64)
+                P[rr * n + c] = c_rank2c(P[rr * n + c], vr, S.wv[c], wr, S.vv[c]);
         }
         __syncthreads();
     }
@@ -551,10 +676,11 @@ __device__ void wg_backtransform_reg(WgLds& S, const double2* __restrict__ P, do
                     for (int t = 0; t < 4; ++t) y = c_fmac(v[G * (4 * gq + t) + g], u[4 * gq + t], y);
                 }
             }
-            y.x += __shfl_xor(y.x, 1, 64);
-            y.y += __shfl_xor(y.y, 1, 64);
-            y.x += __shfl_xor(y.x, 2, 64);
-            y.y += __shfl_xor(y.y, 2, 64);
+            // the column's four threads are a DPP quad
+            y.x += __builtin_amdgcn_update_dpp(0.0, y.x, 0xB1, 0xF, 0xF, false);
+            y.y += __builtin_amdgcn_update_dpp(0.0, y.y, 0xB1, 0xF, 0xF, false);
+            y.x += __builtin_amdgcn_update_dpp(0.0, y.x, 0x4E, 0xF, 0xF, false);
+            y.y += __builtin_amdgcn_update_dpp(0.0, y.y, 0x4E, 0xF, 0xF, false);
             const double2 ty = c_mul(tau, y);
 #pragma unroll
             for (int gq = 0; gq < RJ / 4; ++gq) {
@@ -674,7 +800,10 @@ __device__ bool wg_eigen_velocities(WgLds& S, const WgScratch& X, const ModelDev
                                     const int* __restrict__ r0, int i0, int max_iter) {
     const int n = md.n;
     wg_build(S, X, md, T0, T1, r0, i0);
-    wg_tridiag(S, X.P, n);
+    if constexpr (SMALL)
+        wg_tridiag_cols(S, X.P, n);
+    else
+        wg_tridiag(S, X.P, n);
     double pivmin, span;
     wg_bisect(S, n, pivmin, span);
     int close = 0;
