@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstddef>
 #include <cstdint>
 
 #include "kubo_cplx.h"
@@ -24,12 +25,18 @@ constexpr int kWgMaxN = 128;
 constexpr int kTile = 32;
 
 struct WgLds {
+    // used by the Householder reduction
     double2 xv[kWgMaxN];
     double2 vv[kWgMaxN];
     double2 wv[kWgMaxN];
     double2 tau[kWgMaxN];
     double d[kWgMaxN];
     double e[kWgMaxN];
+    double2 ph[16];
+    double red[2 * (kWgThreads / 64)];
+    int flag;
+    // dead during the reduction from lam on: the n <= 64 kernels put the
+    // matrix there (over the end of the struct, into their dynamic extension)
     double lam[kWgMaxN];
     double cs[2 * kWgMaxN];
     double en[kWgMaxN];
@@ -38,12 +45,18 @@ struct WgLds {
     double Om[kWgMaxN];
     double phi[kWgMaxN];
     double dphi[kWgMaxN];
-    double2 ph[16];
-    double red[2 * (kWgThreads / 64)];
-    int flag;
     double2 ta[kTile * (kTile + 1)];
-    double2 tb[kTile * (kTile + 1)];
 };
+
+// The n <= 64 kernels get 80 KB of LDS per workgroup (two workgroups per CU):
+// the n x n matrix of the Householder reduction from S.lam on, and the four
+// wavefronts' partial sums of p (4 x 64 complex) at the very end.
+constexpr size_t kWgSmallLds = 80 * 1024;
+constexpr int kWgSmallN = 64;
+constexpr size_t kWgSmallPart = sizeof(double2) * (kWgThreads / 64) * kWgSmallN;
+static_assert(sizeof(WgLds) <= kWgSmallLds, "LDS layout");
+static_assert(offsetof(WgLds, lam) + sizeof(double2) * kWgSmallN * kWgSmallN <= kWgSmallLds - kWgSmallPart,
+              "LDS matrix region");
 
 // Per-workgroup scratch: seven n_max x n_max complex matrices.
 struct WgScratch {
@@ -237,11 +250,12 @@ __device__ void wg_tridiag(WgLds& S, double2* __restrict__ P, int n) {
 
 // ---------------------------------------------------------------------------
 // step 2a for n <= 64, the same reduction restructured (measured faster there;
-// wg_tridiag stays faster at n = 128).  Per step: column k through LDS; p = A22 v in column form (A22 is Hermitian,
+// wg_tridiag stays faster at n = 128), run on an LDS copy of the matrix.  Per
+// step: column k through LDS; p = A22 v in column form (A22 is Hermitian,
 // p_r = sum_c conj(A_cr) v_c), each wavefront summing every fourth c with
-// lanes over r (coalesced reads of the scratch rows), the four partial sums
-// combined through LDS (S.ta); the rank-2 update with wavefronts over rows and
-// lanes over columns.  Six barriers per step.
+// lanes over r, the four partial sums combined through an LDS buffer (part);
+// the rank-2 update with wavefronts over rows and lanes over columns.  Six
+// barriers per step.
 // ---------------------------------------------------------------------------
 // workgroup sum with one barrier; red[base .. base+3] must not be reused
 // before the next barrier
@@ -252,10 +266,10 @@ __device__ __forceinline__ double wg_sum1(double v, double* red, int base) {
     return (red[base] + red[base + 1]) + (red[base + 2] + red[base + 3]);
 }
 
-__device__ void wg_tridiag_cols(WgLds& S, double2* __restrict__ P, int n) {
+__device__ void wg_tridiag_cols(WgLds& S, double2* __restrict__ P, int n, double2* __restrict__ part) {
+    // part: [NW][kWgSmallN] partial sums of p (n <= kWgSmallN)
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     constexpr int NW = kWgThreads / 64;
-    double2* part = S.ta;  // [NW][kWgMaxN] partial sums of p
     auto rcp = [](double x) {
         const double r = __builtin_amdgcn_rcp(x);
         return fma(r, fma(-x, r, 1.0), r);
@@ -305,14 +319,14 @@ __device__ void wg_tridiag_cols(WgLds& S, double2* __restrict__ P, int n) {
                 a1 = c_fmac(P[(c + NW) * n + r], S.vv[c + NW], a1);
             }
             if (c < n) a0 = c_fmac(P[c * n + r], S.vv[c], a0);
-            part[w * kWgMaxN + r] = c_add(a0, a1);
+            part[w * kWgSmallN + r] = c_add(a0, a1);
         }
         __syncthreads();
         double2 p = c_make(0.0, 0.0), v = p;
         double mpart = 0.0;
         const int r = k + 1 + tid;
         if (r < n) {
-            p = c_add(c_add(part[r], part[kWgMaxN + r]), c_add(part[2 * kWgMaxN + r], part[3 * kWgMaxN + r]));
+            p = c_add(c_add(part[r], part[kWgSmallN + r]), c_add(part[2 * kWgSmallN + r], part[3 * kWgSmallN + r]));
             v = S.vv[r];
             mpart = v.x * p.x + v.y * p.y;
         }
@@ -800,10 +814,19 @@ __device__ bool wg_eigen_velocities(WgLds& S, const WgScratch& X, const ModelDev
                                     const int* __restrict__ r0, int i0, int max_iter) {
     const int n = md.n;
     wg_build(S, X, md, T0, T1, r0, i0);
-    if constexpr (SMALL)
-        wg_tridiag_cols(S, X.P, n);
-    else
+    if constexpr (SMALL) {
+        // on an LDS copy of the matrix (see kWgSmallLds)
+        unsigned char* base = reinterpret_cast<unsigned char*>(&S);
+        double2* Pl = reinterpret_cast<double2*>(base + offsetof(WgLds, lam));
+        double2* part = reinterpret_cast<double2*>(base + kWgSmallLds - kWgSmallPart);
+        for (int e = threadIdx.x; e < n * n; e += kWgThreads) Pl[e] = X.P[e];
+        __syncthreads();
+        wg_tridiag_cols(S, Pl, n, part);
+        for (int e = threadIdx.x; e < n * n; e += kWgThreads) X.P[e] = Pl[e];
+        __syncthreads();
+    } else {
         wg_tridiag(S, X.P, n);
+    }
     double pivmin, span;
     wg_bisect(S, n, pivmin, span);
     int close = 0;
@@ -1042,7 +1065,7 @@ static hipError_t wg_attrs() {
                          reinterpret_cast<const void*>(&k_adjoint_wg<true>),
                          reinterpret_cast<const void*>(&k_adjoint_wg<false>)};
     for (const void* f : fns) {
-        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(WgLds));
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kWgSmallLds);
         if (e != hipSuccess) return e;
     }
     g_wg_attr = true;
@@ -1057,7 +1080,7 @@ hipError_t launch_forward_wg(const WgLaunch& L, int np, hipStream_t s) {
     if (e != hipSuccess) return e;
     const int grid = L.item_count < L.max_groups ? L.item_count : L.max_groups;
     if (np <= 64)
-        hipLaunchKernelGGL(k_forward_wg<true>, dim3(grid), dim3(kWgThreads), sizeof(WgLds), s, L);
+        hipLaunchKernelGGL(k_forward_wg<true>, dim3(grid), dim3(kWgThreads), kWgSmallLds, s, L);
     else
         hipLaunchKernelGGL(k_forward_wg<false>, dim3(grid), dim3(kWgThreads), sizeof(WgLds), s, L);
     return hipGetLastError();
@@ -1069,7 +1092,7 @@ hipError_t launch_adjoint_wg(const WgLaunch& L, int np, hipStream_t s) {
     if (e != hipSuccess) return e;
     const int grid = L.item_count < L.max_groups ? L.item_count : L.max_groups;
     if (np <= 64)
-        hipLaunchKernelGGL(k_adjoint_wg<true>, dim3(grid), dim3(kWgThreads), sizeof(WgLds), s, L);
+        hipLaunchKernelGGL(k_adjoint_wg<true>, dim3(grid), dim3(kWgThreads), kWgSmallLds, s, L);
     else
         hipLaunchKernelGGL(k_adjoint_wg<false>, dim3(grid), dim3(kWgThreads), sizeof(WgLds), s, L);
     return hipGetLastError();
