@@ -46,6 +46,7 @@ struct WgLds {
     double phi[kWgMaxN];
     double dphi[kWgMaxN];
     double2 ta[kTile * (kTile + 1)];
+    double2 tb[kTile * (kTile + 1)];
 };
 
 // The n <= 64 kernels get 80 KB of LDS per workgroup (two workgroups per CU):
@@ -757,7 +758,7 @@ __device__ __forceinline__ wg_v4d wg_mfma16(double a, double b, wg_v4d c) {
 }
 
 template <class FA, class FB>
-__device__ void wg_gemm(WgLds& S, double2* __restrict__ C, int n, FA LA, FB LB) {
+__device__ void wg_gemm_mfma(WgLds& S, double2* __restrict__ C, int n, FA LA, FB LB) {
     (void)S;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int g = lane >> 4, c = lane & 15;
@@ -807,6 +808,59 @@ __device__ void wg_gemm(WgLds& S, double2* __restrict__ C, int n, FA LA, FB LB) 
     __syncthreads();
 }
 
+// The same product through 32 x 32 LDS tiles on the vector ALUs (LA and LB as
+// above).  Used for n > 64: there the matrix-core version measured slower in
+// the adjoint (its operands come uncoalesced from a scratch slice that no
+// longer fits in the caches, and its accumulators cost the kernel its second
+// wavefront per SIMD).
+template <class FA, class FB>
+__device__ void wg_gemm_tiles(WgLds& S, double2* __restrict__ C, int n, FA LA, FB LB) {
+    const int tid = threadIdx.x;
+    const int ti = tid >> 4, tj = tid & 15;  // 2 x 2 outputs per thread
+    const int nt = (n + kTile - 1) / kTile;
+    for (int bi = 0; bi < nt; ++bi)
+        for (int bj = 0; bj < nt; ++bj) {
+            double2 acc[2][2];
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) acc[a][b] = c_make(0.0, 0.0);
+            for (int bk = 0; bk < nt; ++bk) {
+                for (int e = tid; e < kTile * kTile; e += kWgThreads) {
+                    const int r = e / kTile, c = e - (e / kTile) * kTile;
+                    const int gi = bi * kTile + r, gk = bk * kTile + c;
+                    S.ta[r * (kTile + 1) + c] = (gi < n && gk < n) ? LA(gi, gk) : c_make(0.0, 0.0);
+                    const int gk2 = bk * kTile + r, gj = bj * kTile + c;
+                    S.tb[r * (kTile + 1) + c] = (gk2 < n && gj < n) ? LB(gk2, gj) : c_make(0.0, 0.0);
+                }
+                __syncthreads();
+                for (int kk = 0; kk < kTile; ++kk) {
+                    const double2 a0 = S.ta[(2 * ti) * (kTile + 1) + kk];
+                    const double2 a1 = S.ta[(2 * ti + 1) * (kTile + 1) + kk];
+                    const double2 b0 = S.tb[kk * (kTile + 1) + 2 * tj];
+                    const double2 b1 = S.tb[kk * (kTile + 1) + 2 * tj + 1];
+                    acc[0][0] = c_fma(a0, b0, acc[0][0]);
+                    acc[0][1] = c_fma(a0, b1, acc[0][1]);
+                    acc[1][0] = c_fma(a1, b0, acc[1][0]);
+                    acc[1][1] = c_fma(a1, b1, acc[1][1]);
+                }
+                __syncthreads();
+            }
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) {
+                    const int gi = bi * kTile + 2 * ti + a, gj = bj * kTile + 2 * tj + b;
+                    if (gi < n && gj < n) C[gi * n + gj] = acc[a][b];
+                }
+        }
+    __syncthreads();
+}
+
+template <bool MFMA, class FA, class FB>
+__device__ __forceinline__ void wg_gemm(WgLds& S, double2* __restrict__ C, int n, FA LA, FB LB) {
+    if constexpr (MFMA)
+        wg_gemm_mfma(S, C, n, LA, LB);
+    else
+        wg_gemm_tiles(S, C, n, LA, LB);
+}
+
 // Steps 1-3: E (S.E), U, and A = U^+ v_x U in X.VX, B = U^+ v_y U in X.VY.
 template <bool SMALL>
 __device__ bool wg_eigen_velocities(WgLds& S, const WgScratch& X, const ModelDev& md,
@@ -852,13 +906,13 @@ __device__ bool wg_eigen_velocities(WgLds& S, const WgScratch& X, const ModelDev
     double2* W = X.W;
     double2* VX = X.VX;
     double2* VY = X.VY;
-    wg_gemm(S, W, n, [=](int i, int k) { return VX[i * n + k]; },
+    wg_gemm<SMALL>(S, W, n, [=](int i, int k) { return VX[i * n + k]; },
             [=](int k, int j) { return U[k * n + j]; });
-    wg_gemm(S, VX, n, [=](int i, int k) { return c_conj(U[k * n + i]); },
+    wg_gemm<SMALL>(S, VX, n, [=](int i, int k) { return c_conj(U[k * n + i]); },
             [=](int k, int j) { return W[k * n + j]; });
-    wg_gemm(S, W, n, [=](int i, int k) { return VY[i * n + k]; },
+    wg_gemm<SMALL>(S, W, n, [=](int i, int k) { return VY[i * n + k]; },
             [=](int k, int j) { return U[k * n + j]; });
-    wg_gemm(S, VY, n, [=](int i, int k) { return c_conj(U[k * n + i]); },
+    wg_gemm<SMALL>(S, VY, n, [=](int i, int k) { return c_conj(U[k * n + i]); },
             [=](int k, int j) { return W[k * n + j]; });
     return ok;
 }
@@ -866,9 +920,9 @@ __device__ bool wg_eigen_velocities(WgLds& S, const WgScratch& X, const ModelDev
 // ---------------------------------------------------------------------------
 // k_forward_wg
 // ---------------------------------------------------------------------------
-// SMALL (n <= 64): register back-transformation; both instantiations run two waves per SIMD
+// SMALL (n <= 64): LDS-resident reduction, register back-transformation, matrix-core GEMMs
 template <bool SMALL>
-__global__ __launch_bounds__(kWgThreads, 2) void k_forward_wg(WgLaunch a) {
+__global__ __launch_bounds__(kWgThreads, SMALL ? 2 : 1) void k_forward_wg(WgLaunch a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     WgLds& S = *reinterpret_cast<WgLds*>(smem_raw);
     const double eta2 = a.eta * a.eta;
@@ -935,7 +989,7 @@ __device__ __forceinline__ void wg_phi_at(double x, const double* __restrict__ e
 // kubo_device.hip for the formulas); writes the block's pencil partials.
 // ---------------------------------------------------------------------------
 template <bool SMALL>
-__global__ __launch_bounds__(kWgThreads, 2) void k_adjoint_wg(WgLaunch a) {
+__global__ __launch_bounds__(kWgThreads, SMALL ? 2 : 1) void k_adjoint_wg(WgLaunch a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     WgLds& S = *reinterpret_cast<WgLds*>(smem_raw);
     const double eta2 = a.eta * a.eta;
@@ -1022,19 +1076,19 @@ __global__ __launch_bounds__(kWgThreads, 2) void k_adjoint_wg(WgLaunch a) {
             double2* VY = X.VY;
             const double* K = X.K;
             // Hbar = U Hbar' U^+  (P = Hbar' U^+, W = U P)
-            wg_gemm(S, P, n, [=](int i, int k) { return W[i * n + k]; },
+            wg_gemm<SMALL>(S, P, n, [=](int i, int k) { return W[i * n + k]; },
                     [=](int k, int j) { return c_conj(U[j * n + k]); });
-            wg_gemm(S, W, n, [=](int i, int k) { return U[i * n + k]; },
+            wg_gemm<SMALL>(S, W, n, [=](int i, int k) { return U[i * n + k]; },
                     [=](int k, int j) { return P[k * n + j]; });
             // vbar_x = U Abar U^+, Abar = (i/N) K o B   (P = Abar U^+, VY = U P)
-            wg_gemm(S, P, n, [=](int i, int k) { return c_scale(invN * K[i * n + k], c_i(VY[i * n + k])); },
+            wg_gemm<SMALL>(S, P, n, [=](int i, int k) { return c_scale(invN * K[i * n + k], c_i(VY[i * n + k])); },
                     [=](int k, int j) { return c_conj(U[j * n + k]); });
-            wg_gemm(S, VY, n, [=](int i, int k) { return U[i * n + k]; },
+            wg_gemm<SMALL>(S, VY, n, [=](int i, int k) { return U[i * n + k]; },
                     [=](int k, int j) { return P[k * n + j]; });
             // vbar_y = U Bbar U^+, Bbar = -(i/N) K o A  (P = Bbar U^+, VX = U P)
-            wg_gemm(S, P, n, [=](int i, int k) { return c_scale(-invN * K[i * n + k], c_i(VX[i * n + k])); },
+            wg_gemm<SMALL>(S, P, n, [=](int i, int k) { return c_scale(-invN * K[i * n + k], c_i(VX[i * n + k])); },
                     [=](int k, int j) { return c_conj(U[j * n + k]); });
-            wg_gemm(S, VX, n, [=](int i, int k) { return U[i * n + k]; },
+            wg_gemm<SMALL>(S, VX, n, [=](int i, int k) { return U[i * n + k]; },
                     [=](int k, int j) { return P[k * n + j]; });
             for (long long e = threadIdx.x; e < (long long)md.nR0 * nn; e += kWgThreads) {
                 const int rho = (int)(e / nn);
