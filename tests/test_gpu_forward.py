@@ -104,6 +104,20 @@ def test_degenerate_spectrum_parity(torch, oracle, n):
     assert_sigma_parity(got[0], ref, sabs, what=f"doubled n={2 * n}")
 
 
+@pytest.mark.parametrize("n", [12, 28])
+def test_graded_spectrum_parity(torch, oracle, n):
+    """Orbitals scaled over four decades (D t D): many eigenvalues far below the spectral
+    radius, so the eigenvalue search keeps bracketing to the absolute tolerance instead of
+    converging by Newton steps, and the twisted vectors see strongly graded pivots."""
+    base = synth.random_model(n, 1, 1.0, 660 + n)
+    d = 10.0 ** np.linspace(-3.0, 1.0, n)
+    m = synth.TBModel(t=base.t * d[None, :, None] * d[None, None, :], R=base.R.copy())
+    ef = np.array([-2.0, -1e-3, 0.0, 1e-3, 2.0])
+    got, _ = run_gpu(torch, [m], (4, 3, 2), ef, 1e-3, 0.01)
+    ref, sabs = oracle.ahc(m.t, m.R, (4, 3, 2), ef, 1e-3, 0.01, with_sabs=True)
+    assert_sigma_parity(got[0], ref, sabs, what=f"graded n={n}")
+
+
 @pytest.mark.parametrize("u", [-1.0, 1.0, 3.0])
 def test_qwz_quantised_on_gpu(torch, u):
     m = synth.qwz_model(u)
