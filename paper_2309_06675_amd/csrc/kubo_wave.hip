@@ -1,24 +1,30 @@
-// kubo_wave.hip -- one wavefront per k-point: the forward pipeline for n <= 32.
+// kubo_wave.hip -- one wavefront per k-point: the forward pipeline for n <= 32
+// and its adjoint.
 //
 // Eigensolver: the route the paper batched from EISPACK for complex Hermitian
-// matrices (Householder reduction to a real symmetric tridiagonal matrix,
-// implicit QL iterations with eigenvector accumulation, back-transformation),
-// restated for a 64-lane wavefront instead of one vector lane per matrix:
-//   * Householder: lane r owns row r of the trailing block; the reflector of
+// matrices (Householder reduction to a real symmetric tridiagonal matrix, the
+// tridiagonal eigenproblem, back-transformation), restated for a 64-lane
+// wavefront instead of one vector lane per matrix:
+//   * Householder: the matrix stays in registers, lane pair (2i, 2i+1) holding
+//     row i with the columns interleaved between the two lanes; the reflector of
 //     column k is chosen so the sub-diagonal element is real, making T real.
-//   * QL: the tridiagonal (d, e) lives one element per lane; the rotation
-//     chain reads and writes lanes by index (uniform across the wave), and the
-//     rotations of a sweep are applied to Z afterwards, one row per lane, in a
-//     single streaming pass.
-//   * Back-transformation U = H_0 ... H_{n-2} Z: lane c owns column c.
-// Velocities (n > 8): A = U^+ v_x U and B = U^+ v_y U are dense complex
-// products, done on the FP64 matrix cores (16x16x4 MFMA, four real products
-// per complex one).  v is staged in LDS, U is read once per k-point into the
-// MFMA operand layout and reused by both products of both velocities, and the
-// first product's accumulators feed the second directly (X = v U, then
-// M = X^+ U with the contraction index permuted so that every lane already
-// holds its operand).  The curvature is taken from the accumulator tiles.
-// For n <= 8: W = v U with v built on the fly, U^+ W accumulated in registers.
+//   * Eigenvalues: Sturm counts with safeguarded Newton steps, two lanes per
+//     eigenvalue; eigenvectors of T: one twisted factorisation per lane pair.
+//     Spectra with a relative gap below 1e-3 take implicit QL instead (the
+//     tridiagonal one element per lane, the rotations applied to Z one row per
+//     lane).
+//   * Back-transformation U = H_0 ... H_{n-2} Z: lane pair per column, rows
+//     interleaved between the two lanes.
+// H, v_x and v_y are summed over their upper triangles (they are Hermitian) and
+// mirrored.  Velocities (n > 8): A = U^+ v_x U and B = U^+ v_y U are dense
+// complex products, done on the FP64 matrix cores (16x16x4 MFMA, four real
+// products per complex one).  v is staged in LDS, U is read once per k-point
+// into the MFMA operand layout and reused by both products of both
+// velocities, and the first product's accumulators feed the second directly
+// (X = v U, then M = X^+ U with the contraction index permuted so that every
+// lane already holds its operand).  The curvature is taken from the
+// accumulator tiles.  For n <= 8: W = v U with v built on the fly, U^+ W
+// accumulated in registers.
 #include <hip/hip_runtime.h>
 
 #include <cmath>

@@ -2,12 +2,15 @@
 // forward and adjoint.
 //
 // Same method as the one-wavefront path (Householder reduction to a real
-// tridiagonal matrix, Sturm-count multisection for the eigenvalues, twisted
-// factorisations for the eigenvectors with an implicit-QL path for clustered
-// spectra, back-transformation, U^+ v U), but the n x n matrices of the k-point
-// being processed live in a per-workgroup slice of the workspace (it stays in
-// L2 / the last-level cache) instead of LDS, which cannot hold them at n = 128.
-// Products of matrices go through 32 x 32 LDS tiles.
+// tridiagonal matrix, Sturm counts with safeguarded Newton steps for the
+// eigenvalues, twisted factorisations for the eigenvectors with an implicit-QL
+// path for clustered spectra, back-transformation, U^+ v U), but the n x n
+// matrices of the k-point being processed live in a per-workgroup slice of the
+// workspace (it stays in L2 / the last-level cache) instead of registers and
+// LDS, which cannot hold them all at n = 128.  Two instantiations: n <= 64
+// (reduction on an LDS copy, register back-transformation, products on the
+// FP64 matrix cores) and n <= 128 (reduction in the slice, LDS-staged
+// back-transformation, products through 32 x 32 LDS tiles).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
