@@ -33,9 +33,11 @@
  *     non-OK return means nothing was enqueued.  Results are bitwise identical
  *     from run to run (fixed reduction order, no floating-point atomics).
  *   - The library never allocates device memory: the caller passes a
- *     workspace of at least the size kubo_plan reports.  The first call with a
- *     given workspace uploads the plan's index tables into it and synchronises
- *     the stream; the caller must not modify the workspace between calls.
+ *     workspace of at least the size kubo_plan reports.  A call uploads the
+ *     plan's index tables into the workspace, and synchronises the stream,
+ *     when that workspace does not hold them already (its first use by the
+ *     plan, or another plan ran on it since); plans may therefore take turns
+ *     on one workspace.  The caller must not modify a workspace between calls.
  *   - A plan is not safe to use from two threads at once.
  */
 #ifndef KUBO_H

@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <set>
 #include <tuple>
@@ -106,7 +107,8 @@ struct kubo_plan_s {
     int wg_groups = 512;
     std::vector<unsigned char> blob;
     size_t tab_off[10] = {0};
-    const void* uploaded_ws = nullptr;
+    unsigned long long id = 0;           // unique per plan (never reused)
+    std::set<const void*> used_ws;       // workspaces this plan has run on
     CachedGraph graph_fwd, graph_bwd;
     int max_groups = 2048;
     int max_group = 1;  // most lattice vectors sharing one R_x value
@@ -119,6 +121,7 @@ struct kubo_plan_s {
     std::vector<TimeRec> trec;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> tpool;
     bool capturing = false;
+    bool no_events = false;  // no event records (the no-allocation forward)
 };
 
 namespace {
@@ -408,6 +411,13 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
                 for (int k = 0; k < kNumClasses; ++k) most = std::max(most, c.cls[k].count);
         P->wg_groups = std::min(P->wg_groups, most);
         if (P->wg_groups >= 8) P->wg_groups &= ~7;  // whole XCD rounds
+        // only the workgroup classes use the per-workgroup scratch
+        bool any_wg = false;
+        for (const kubo_plan_s::ChunkSet* cs : {&P->fwd, &P->bwd})
+            for (const Chunk& c : cs->chunks)
+                for (int k = 0; k < kNumClasses; ++k)
+                    if (!kClasses[k].wave && c.cls[k].count > 0) any_wg = true;
+        if (!any_wg) P->slot_elems = 0;
     }
     P->off_scratch = off;
     off = align_up(off + (size_t)P->wg_groups * (size_t)P->slot_elems * 16);
@@ -463,13 +473,31 @@ kubo_status validate(const kubo_model_desc* models, int n_models, int nF, uint32
         if ((x) != hipSuccess) return KUBO_E_HIP;   \
     } while (0)
 
+// Which plan's index tables a workspace holds.  Plans can take turns on one
+// workspace (and every no-allocation call on a device shares one), so the
+// owner is looked up on every call and the tables are uploaded again whenever
+// another plan wrote its own there in between.  Keys are device addresses,
+// unique across devices; owners are plan ids, never reused.
+std::mutex g_ws_mu;
+std::map<const void*, unsigned long long> g_ws_owner;
+unsigned long long g_next_plan_id = 1;
+
 kubo_status ensure_tables(kubo_plan_s* P, void* ws, hipStream_t s) {
-    if (P->uploaded_ws == ws) return KUBO_OK;
+    std::lock_guard<std::mutex> lock(g_ws_mu);
+    auto it = g_ws_owner.find(ws);
+    if (it != g_ws_owner.end() && it->second == P->id) return KUBO_OK;
     HIP_TRY(hipMemcpyAsync(static_cast<unsigned char*>(ws) + P->off_tables, P->blob.data(),
                            P->blob.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));
-    P->uploaded_ws = ws;
+    g_ws_owner[ws] = P->id;
+    P->used_ws.insert(ws);
     return KUBO_OK;
+}
+
+void forget_plan(const kubo_plan_s* P) {
+    std::lock_guard<std::mutex> lock(g_ws_mu);
+    for (auto it = g_ws_owner.begin(); it != g_ws_owner.end();)
+        it = (it->second == P->id) ? g_ws_owner.erase(it) : std::next(it);
 }
 
 // Event pair around one per-k launch (only outside graph capture).
@@ -479,7 +507,7 @@ struct TimedScope {
     bool on = false;
     kubo_plan_s::TimeRec rec{};
     TimedScope(kubo_plan_s* P_, hipStream_t s_, int which, long long kpts) : P(P_), s(s_) {
-        if (!(P->flags & KUBO_F_TIMING) || P->capturing) return;
+        if (!(P->flags & KUBO_F_TIMING) || P->capturing || P->no_events) return;
         if (P->tpool.empty()) {
             hipEvent_t a, b;
             if (hipEventCreate(&a) != hipSuccess) return;
@@ -658,6 +686,43 @@ kubo_status run_graph(kubo_plan_s* plan, CachedGraph& g, const GraphKey& key, hi
 
 }  // namespace
 
+namespace kubo {
+
+kubo_status ahc_enqueue(kubo_plan_s* plan, const double* t, const double* e_fermi, double eta,
+                        double kT, double* sigma, void* workspace, size_t workspace_bytes,
+                        void* stream, bool allow_graph) {
+    if (!plan || !t || !e_fermi || !sigma) return KUBO_E_INVALID;
+    if (!finite_nonneg(eta) || !finite_nonneg(kT)) return KUBO_E_INVALID;
+    if (!workspace || workspace_bytes < plan->total) return KUBO_E_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    unsigned char* ws = static_cast<unsigned char*>(workspace);
+    kubo_status st = ensure_tables(plan, workspace, s);
+    if (st != KUBO_OK) return st;
+    if (allow_graph && (plan->flags & KUBO_F_GRAPH) && s != nullptr) {
+        GraphKey key{};
+        key.p[0] = t;
+        key.p[1] = e_fermi;
+        key.p[2] = sigma;
+        key.p[3] = workspace;
+        key.d[0] = eta;
+        key.d[1] = kT;
+        key.stream = stream;
+        return run_graph(plan, plan->graph_fwd, key, s, [&]() {
+            return enqueue_forward(plan, t, e_fermi, eta, kT, sigma, ws, s);
+        });
+    }
+    if (!allow_graph) {
+        // no event records either: the caller may not be able to create them
+        plan->no_events = true;
+        st = enqueue_forward(plan, t, e_fermi, eta, kT, sigma, ws, s);
+        plan->no_events = false;
+        return st;
+    }
+    return enqueue_forward(plan, t, e_fermi, eta, kT, sigma, ws, s);
+}
+
+}  // namespace kubo
+
 extern "C" {
 
 kubo_status kubo_plan(kubo_plan_t* plan, const kubo_model_desc* models, int32_t n_models,
@@ -673,6 +738,10 @@ kubo_status kubo_plan(kubo_plan_t* plan, const kubo_model_desc* models, int32_t 
         delete P;
         return st;
     }
+    {
+        std::lock_guard<std::mutex> lock(g_ws_mu);
+        P->id = g_next_plan_id++;
+    }
     *plan = P;
     *workspace_bytes = P->total;
     return KUBO_OK;
@@ -681,27 +750,8 @@ kubo_status kubo_plan(kubo_plan_t* plan, const kubo_model_desc* models, int32_t 
 kubo_status kubo_ahc(kubo_plan_t plan, const double* t, const double* e_fermi, double eta,
                      double kT, double* sigma, void* workspace, size_t workspace_bytes,
                      void* stream) {
-    if (!plan || !t || !e_fermi || !sigma) return KUBO_E_INVALID;
-    if (!finite_nonneg(eta) || !finite_nonneg(kT)) return KUBO_E_INVALID;
-    if (!workspace || workspace_bytes < plan->total) return KUBO_E_WORKSPACE;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    unsigned char* ws = static_cast<unsigned char*>(workspace);
-    kubo_status st = ensure_tables(plan, workspace, s);
-    if (st != KUBO_OK) return st;
-    if ((plan->flags & KUBO_F_GRAPH) && s != nullptr) {
-        GraphKey key{};
-        key.p[0] = t;
-        key.p[1] = e_fermi;
-        key.p[2] = sigma;
-        key.p[3] = workspace;
-        key.d[0] = eta;
-        key.d[1] = kT;
-        key.stream = stream;
-        return run_graph(plan, plan->graph_fwd, key, s, [&]() {
-            return enqueue_forward(plan, t, e_fermi, eta, kT, sigma, ws, s);
-        });
-    }
-    return enqueue_forward(plan, t, e_fermi, eta, kT, sigma, ws, s);
+    return kubo::ahc_enqueue(plan, t, e_fermi, eta, kT, sigma, workspace, workspace_bytes, stream,
+                             true);
 }
 
 kubo_status kubo_ahc_backward(kubo_plan_t plan, const double* t, const double* e_fermi,
@@ -733,7 +783,7 @@ kubo_status kubo_ahc_backward(kubo_plan_t plan, const double* t, const double* e
 }
 
 kubo_status kubo_plan_device_status(kubo_plan_t plan, const void* workspace, void* stream) {
-    if (!plan || !workspace || plan->uploaded_ws != workspace) return KUBO_E_INVALID;
+    if (!plan || !workspace || !plan->used_ws.count(workspace)) return KUBO_E_INVALID;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (hipStreamSynchronize(s) != hipSuccess) return KUBO_E_HIP;
     unsigned v = 0;
@@ -787,6 +837,7 @@ void kubo_plan_destroy(kubo_plan_t plan) {
         if (g->exec) (void)hipGraphExecDestroy(g->exec);
         if (g->graph) (void)hipGraphDestroy(g->graph);
     }
+    forget_plan(plan);
     delete plan;
 }
 

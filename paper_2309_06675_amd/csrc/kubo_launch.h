@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "../../include/kubo.h"
 #include "kubo_internal.h"
 
 namespace kubo {
@@ -65,5 +66,11 @@ hipError_t launch_gsym(const Tables& tb, int n_models, long long total, double* 
                        hipStream_t s);
 hipError_t launch_reduce(const Tables& tb, int n_models, int nF, const double* partial,
                          double* sigma, unsigned* status, hipStream_t s);
+
+// The body of kubo_ahc on a given workspace.  allow_graph = false: eager
+// launches only, and no timing events (the no-allocation entry point).
+kubo_status ahc_enqueue(kubo_plan_t plan, const double* t, const double* e_fermi, double eta,
+                        double kT, double* sigma, void* workspace, size_t workspace_bytes,
+                        void* stream, bool allow_graph);
 
 }  // namespace kubo
