@@ -32,6 +32,12 @@
  *   g_nm     = 1 / ((E_n - E_m)^2 + eta^2)
  *   sigma_j  = (2/N_k) sum_k sum_{n<m} (f_j(E_n) - f_j(E_m)) g_nm Im(A_nm B_mn)
  *
+ * oracle_ahc_tensor evaluates the same band-pair sum for other pairs of
+ * operators of the general response Eq. (1): the Hall tensor components
+ * sigma_yz (v_y, v_z) and sigma_zx (v_z, v_x) next to sigma_xy, and the spin
+ * Hall conductivity (spin current Js_x = (s_z v_x + v_x s_z)/2 with a diagonal
+ * s_z, field along y).
+ *
  * The reference gradient (oracle_ahc_grad) is derived in the design notes;
  * the paper has no adjoint.  It uses the divided-difference form of the
  * eigenvector term so that it stays finite through degeneracies.
@@ -458,6 +464,179 @@ int oracle_ahc(int n, int nR, const int* R, const double* t, const int* grid, lo
         sigma[j] = nval(&s) / (double)Nk;
         if (sabs) sabs[j] = nval(&sa) / (double)Nk;
         if (sband) sband[j] = nval(&sb) / (double)Nk;
+    }
+    free(csum);
+    free(cabsum);
+    free(cband);
+    return bad ? -1 : 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Other operator pairs of the general response (Eq. (1)): the Hall      */
+/* tensor components xy, yz, zx and the spin Hall component.            */
+/* ------------------------------------------------------------------ */
+
+/* H(k) and the three velocities v_a = dH/dk_a (Hermitian parts), and, when
+ * spin != NULL, the spin current Js_x = (S v_x + v_x S)/2 for the diagonal spin
+ * operator S = diag(spin). */
+static void build_hk3(int n, int nR, const int* R, const cplx* t, const cplx* phase,
+                      const double* spin, cplx* H, cplx* v[3], cplx* js) {
+    size_t nn = (size_t)n * n;
+    cplx* Ht = calloc(nn, sizeof(cplx));
+    cplx* Vt[3];
+    for (int a = 0; a < 3; ++a) Vt[a] = calloc(nn, sizeof(cplx));
+    for (int r = 0; r < nR; ++r) {
+        const cplx* tr = t + (size_t)r * nn;
+        cplx ph = phase[r];
+        cplx pa[3];
+        for (int a = 0; a < 3; ++a) pa[a] = I * (double)R[3 * r + a] * ph;
+        for (size_t e = 0; e < nn; ++e) {
+            Ht[e] += tr[e] * ph;
+            for (int a = 0; a < 3; ++a) Vt[a][e] += tr[e] * pa[a];
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            size_t ij = (size_t)i * n + j, ji = (size_t)j * n + i;
+            H[ij] = 0.5 * (Ht[ij] + conj(Ht[ji]));
+            for (int a = 0; a < 3; ++a) v[a][ij] = 0.5 * (Vt[a][ij] + conj(Vt[a][ji]));
+        }
+    if (spin)
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j)
+                js[(size_t)i * n + j] = 0.5 * (spin[i] + spin[j]) * v[0][(size_t)i * n + j];
+    free(Ht);
+    for (int a = 0; a < 3; ++a) free(Vt[a]);
+}
+
+/* The four components, for every Fermi level j, over the k-slab (normalised by
+ * the full grid):
+ *   c = 0: sigma_xy (operators v_x, v_y)     c = 1: sigma_yz (v_y, v_z)
+ *   c = 2: sigma_zx (v_z, v_x)               c = 3: spin Hall (Js_x, v_y), only
+ *   when spin != NULL (else 0)
+ * each in the pair form sigma_PQ = (2/N_k) sum_k sum_{n<m} (f_n - f_m) g_nm
+ * Im(P'_nm Q'_mn) with P' = U^+ P U, Q' = U^+ Q U.  sigma and sabs are
+ * [4][nF]; sabs (may be NULL) receives (1/N_k) sum of the absolute pair terms
+ * and sband (may be NULL) (1/N_k) sum_k sum_n f_n |Omega^PQ_n| per component.
+ * Returns 0, or -1 if an eigensolve did not converge. */
+int oracle_ahc_tensor(int n, int nR, const int* R, const double* t, const int* grid, long k_begin,
+                      long k_count, int nF, const double* EF, double eta, double kT,
+                      const double* spin, double* sigma, double* sabs, double* sband,
+                      int nthreads) {
+    enum { NC = 4 };
+    long Nk = (long)grid[0] * grid[1] * grid[2];
+    long nchunk = (k_count + ORACLE_KCHUNK - 1) / ORACLE_KCHUNK;
+    size_t per = (size_t)NC * nF;
+    double* csum = calloc((size_t)nchunk * per, sizeof(double));
+    double* cabsum = calloc((size_t)nchunk * per, sizeof(double));
+    double* cband = calloc((size_t)nchunk * per, sizeof(double));
+    int bad = 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel
+    {
+        size_t nn = (size_t)n * n;
+        cplx* phase = malloc((size_t)nR * sizeof(cplx));
+        cplx* H = malloc(nn * sizeof(cplx));
+        cplx* U = malloc(nn * sizeof(cplx));
+        cplx* v[3];
+        cplx* w[4]; /* rotated: v_x, v_y, v_z, Js_x */
+        for (int a = 0; a < 3; ++a) v[a] = malloc(nn * sizeof(cplx));
+        for (int a = 0; a < 4; ++a) w[a] = malloc(nn * sizeof(cplx));
+        cplx* js = malloc(nn * sizeof(cplx));
+        double* E = malloc((size_t)n * sizeof(double));
+        double* fo = malloc((size_t)n * nF * sizeof(double));
+        double* om = malloc((size_t)n * sizeof(double));
+        nsum* acc = malloc(per * sizeof(nsum));
+        nsum* aab = malloc(per * sizeof(nsum));
+        nsum* abd = malloc(per * sizeof(nsum));
+        const int pairs[NC][2] = {{0, 1}, {1, 2}, {2, 0}, {3, 1}};
+#pragma omp for schedule(dynamic, 1)
+        for (long c = 0; c < nchunk; ++c) {
+            for (size_t q = 0; q < per; ++q) {
+                acc[q].s = acc[q].c = 0.0;
+                aab[q].s = aab[q].c = 0.0;
+                abd[q].s = abd[q].c = 0.0;
+            }
+            long kb = k_begin + c * ORACLE_KCHUNK;
+            long ke = kb + ORACLE_KCHUNK;
+            if (ke > k_begin + k_count) ke = k_begin + k_count;
+            for (long f = kb; f < ke; ++f) {
+                long i0, i1, i2;
+                flat_to_ijk(f, grid, &i0, &i1, &i2);
+                grid_phases(nR, R, grid, i0, i1, i2, phase);
+                build_hk3(n, nR, R, (const cplx*)t, phase, spin, H, v, js);
+                if (jacobi_eigh(n, H, E, U) < 0) {
+#pragma omp atomic write
+                    bad = 1;
+                }
+                for (int a = 0; a < 3; ++a) rotate_in(n, U, v[a], w[a]);
+                if (spin) rotate_in(n, U, js, w[3]);
+                for (int a = 0; a < n; ++a)
+                    for (int j = 0; j < nF; ++j) fo[a * nF + j] = occ(E[a], EF[j], kT);
+                for (int comp = 0; comp < NC; ++comp) {
+                    if (comp == 3 && !spin) continue;
+                    const cplx* P = w[pairs[comp][0]];
+                    const cplx* Q = w[pairs[comp][1]];
+                    nsum* ac = acc + (size_t)comp * nF;
+                    nsum* aa = aab + (size_t)comp * nF;
+                    nsum* ab = abd + (size_t)comp * nF;
+                    for (int a = 0; a < n; ++a)
+                        for (int b = a + 1; b < n; ++b) {
+                            double de = E[a] - E[b];
+                            if (eta == 0.0 && de == 0.0) continue;
+                            double wt = 2.0 * bcast_g(de, eta) * cimag(P[a * n + b] * Q[b * n + a]);
+                            for (int j = 0; j < nF; ++j) {
+                                double term = (fo[a * nF + j] - fo[b * nF + j]) * wt;
+                                nadd(&ac[j], term);
+                                nadd(&aa[j], fabs(term));
+                            }
+                        }
+                    if (sband) {
+                        for (int a = 0; a < n; ++a) {
+                            double o = 0.0;
+                            for (int b = 0; b < n; ++b) {
+                                double de = E[a] - E[b];
+                                if (b == a || (eta == 0.0 && de == 0.0)) continue;
+                                o += cimag(P[a * n + b] * Q[b * n + a]) * bcast_g(de, eta);
+                            }
+                            om[a] = fabs(2.0 * o);
+                        }
+                        for (int j = 0; j < nF; ++j)
+                            for (int a = 0; a < n; ++a) nadd(&ab[j], fo[a * nF + j] * om[a]);
+                    }
+                }
+            }
+            for (size_t q = 0; q < per; ++q) {
+                csum[c * per + q] = nval(&acc[q]);
+                cabsum[c * per + q] = nval(&aab[q]);
+                cband[c * per + q] = nval(&abd[q]);
+            }
+        }
+        free(phase);
+        free(H);
+        free(U);
+        for (int a = 0; a < 3; ++a) free(v[a]);
+        for (int a = 0; a < 4; ++a) free(w[a]);
+        free(js);
+        free(E);
+        free(fo);
+        free(om);
+        free(acc);
+        free(aab);
+        free(abd);
+    }
+    for (size_t q = 0; q < per; ++q) {
+        nsum s = {0.0, 0.0}, sa = {0.0, 0.0}, sb = {0.0, 0.0};
+        for (long c = 0; c < nchunk; ++c) {
+            nadd(&s, csum[c * per + q]);
+            nadd(&sa, cabsum[c * per + q]);
+            nadd(&sb, cband[c * per + q]);
+        }
+        sigma[q] = nval(&s) / (double)Nk;
+        if (sabs) sabs[q] = nval(&sa) / (double)Nk;
+        if (sband) sband[q] = nval(&sb) / (double)Nk;
     }
     free(csum);
     free(cabsum);

@@ -54,6 +54,9 @@ def lib():
         L.oracle_ahc.argtypes = [ctypes.c_int, ctypes.c_int, _ip, _dp, _ip, ctypes.c_long,
                                  ctypes.c_long, ctypes.c_int, _dp, ctypes.c_double,
                                  ctypes.c_double, _dp, _dp, _dp, ctypes.c_int]
+        L.oracle_ahc_tensor.argtypes = [ctypes.c_int, ctypes.c_int, _ip, _dp, _ip, ctypes.c_long,
+                                        ctypes.c_long, ctypes.c_int, _dp, ctypes.c_double,
+                                        ctypes.c_double, _dp, _dp, _dp, _dp, ctypes.c_int]
         L.oracle_band_range.argtypes = [ctypes.c_int, ctypes.c_int, _ip, _dp, _ip, _dp, _dp,
                                         ctypes.c_int]
         L.oracle_ahc_grad.argtypes = [ctypes.c_int, ctypes.c_int, _ip, _dp, _ip, ctypes.c_long,
@@ -133,6 +136,39 @@ def ahc(t, R, grid, e_fermi, eta, kT, k_begin=0, k_count=None, nthreads=0, with_
                           int(k_count), nF, _ptr(EF, _dp), float(eta), float(kT), _ptr(sig, _dp),
                           _ptr(sabs, _dp), _ptr(sband, _dp) if with_sabs else None,
                           int(nthreads))
+    if rc != 0:
+        raise RuntimeError("oracle eigensolver did not converge")
+    return (sig, np.maximum(sabs, sband)) if with_sabs else sig
+
+
+TENSOR_COMPONENTS = ("xy", "yz", "zx", "spin_xy")
+
+
+def ahc_tensor(t, R, grid, e_fermi, eta, kT, spin=None, k_begin=0, k_count=None, nthreads=0,
+               with_sabs=False):
+    """[4, nF]: sigma_xy, sigma_yz, sigma_zx and the spin Hall sigma (spin current
+    (s v_x + v_x s)/2, field along y; zero when spin is None) over a k-slab, normalised by
+    the full grid.  spin: the diagonal of s_z in the orbital basis (length n).
+    with_sabs: also return the per-component rounding scale max(S_pair, S_band)."""
+    t, R, n, nR = _model(t, R)
+    grid = _c(grid, np.int32)
+    Nk = int(np.prod(grid.astype(np.int64)))
+    if k_count is None:
+        k_count = Nk - k_begin
+    EF = _c(np.atleast_1d(e_fermi), np.float64)
+    nF = EF.size
+    sp = None
+    if spin is not None:
+        sp = _c(spin, np.float64)
+        assert sp.shape == (n,)
+    sig = np.zeros((4, nF))
+    sabs = np.zeros((4, nF))
+    sband = np.zeros((4, nF))
+    rc = lib().oracle_ahc_tensor(n, nR, _ptr(R, _ip), _ptr(t, _dp), _ptr(grid, _ip), int(k_begin),
+                                 int(k_count), nF, _ptr(EF, _dp), float(eta), float(kT),
+                                 _ptr(sp, _dp) if sp is not None else None, _ptr(sig, _dp),
+                                 _ptr(sabs, _dp), _ptr(sband, _dp) if with_sabs else None,
+                                 int(nthreads))
     if rc != 0:
         raise RuntimeError("oracle eigensolver did not converge")
     return (sig, np.maximum(sabs, sband)) if with_sabs else sig

@@ -196,6 +196,36 @@ def rotate_orbitals(a: TBModel, W: np.ndarray) -> TBModel:
     return TBModel(t=np.einsum("ij,rjk,lk->ril", W, a.t, W.conj()), R=a.R.copy())
 
 
+def qwz_plane_model(u: float, plane: str) -> TBModel:
+    """The Qi-Wu-Zhang lattice in the plane (a, b) = "xy", "yz" or "zx": its first axis
+    carries the sin k sx hopping, its second the sin k sy one (use N = 1 along the third)."""
+    axes = {"xy": (0, 1), "yz": (1, 2), "zx": (2, 0)}[plane]
+    base = qwz_model(u)
+    R = np.zeros_like(base.R)
+    R[:, axes[0]] = base.R[:, 0]
+    R[:, axes[1]] = base.R[:, 1]
+    return TBModel(t=base.t.copy(), R=R)
+
+
+def permute_axes(a: TBModel) -> TBModel:
+    """Cyclic relabelling of the axes: the new y axis is the old x, new z the old y and new x
+    the old z (R' = (R_z, R_x, R_y)); a grid (N0, N1, N2) becomes (N2, N0, N1)."""
+    R = a.R[:, [2, 0, 1]].copy()
+    return TBModel(t=a.t.copy(), R=R)
+
+
+def conjugate(a: TBModel) -> TBModel:
+    """t(R) -> t(R)*: H(k) -> H(-k)*, the time-reversal partner of a spinless block."""
+    return TBModel(t=a.t.conj().copy(), R=a.R.copy())
+
+
+def spin_qwz_pair(u_up: float, u_dn: float):
+    """Spin-up QWZ(u_up) (+) the time-reversal partner of QWZ(u_dn) as the spin-down block,
+    with s_z = (+1, +1, -1, -1): (model, spin diagonal)."""
+    m = direct_sum(qwz_model(u_up), conjugate(qwz_model(u_dn)))
+    return m, np.array([1.0, 1.0, -1.0, -1.0])
+
+
 def swap_xy(a: TBModel) -> TBModel:
     """Exchange the x and y components of every lattice vector."""
     R = a.R.copy()

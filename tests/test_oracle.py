@@ -288,6 +288,52 @@ def test_brute_force_with_lapack_eigensolver(oracle):
     assert np.all(np.abs(s - tot) <= 1e-11 * sabs)
 
 
+def _brute_sigma(m, grid, flats, ef, eta, kT):
+    """sigma over the listed flat k indices with the test's own k enumeration
+    (f = i0 + N0 (i1 + N1 i2), k = 2 pi (i0/N0, i1/N1, i2/N2)), numpy Bloch sums and
+    LAPACK's eigensolver; normalised by the full grid."""
+    N0, N1, N2 = grid
+    tot = np.zeros(len(ef))
+    n = m.n
+    for f in flats:
+        i0, rest = f % N0, f // N0
+        i1, i2 = rest % N1, rest // N1
+        k = 2 * np.pi * np.array([i0 / N0, i1 / N1, i2 / N2])
+        ph = np.exp(1j * (m.R @ k))
+        Ht = np.einsum("r,rij->ij", ph, m.t)
+        Xt = np.einsum("r,rij->ij", 1j * m.R[:, 0] * ph, m.t)
+        Yt = np.einsum("r,rij->ij", 1j * m.R[:, 1] * ph, m.t)
+        H, vx, vy = [(X + X.conj().T) / 2 for X in (Ht, Xt, Yt)]
+        E, U = sla.eigh(H)
+        A = U.conj().T @ vx @ U
+        B = U.conj().T @ vy @ U
+        g = 1.0 / ((E[:, None] - E[None, :]) ** 2 + eta**2)
+        np.fill_diagonal(g, 0.0)
+        Om = -2 * np.sum(np.imag(A * B.T) * g, axis=1)
+        f_occ = 1 / (1 + np.exp((E[:, None] - ef[None, :]) / kT))
+        tot -= (f_occ * Om[:, None]).sum(0)
+    return tot / (N0 * N1 * N2)
+
+
+def test_brute_force_on_a_non_cubic_grid_and_slab(oracle):
+    """A 4 x 3 x 2 grid, and a slab of it, with k enumerated by the test: a mix-up of
+    the axes or of the flat-index order in the oracle's grid handling changes the result
+    (the model's hoppings differ along x, y and z)."""
+    m = S.random_model(4, 1, 1.0, 1199)
+    g = (4, 3, 2)
+    ef = np.array([-0.6, 0.1, 0.9])
+    eta, kT = 2e-2, 0.04
+    full = _brute_sigma(m, g, range(24), ef, eta, kT)
+    s, sabs = oracle.ahc(m.t, m.R, g, ef, eta, kT, with_sabs=True)
+    assert np.all(np.abs(s - full) <= 1e-11 * sabs)
+    part = _brute_sigma(m, g, range(5, 18), ef, eta, kT)
+    sp, sabs_p = oracle.ahc(m.t, m.R, g, ef, eta, kT, k_begin=5, k_count=13, with_sabs=True)
+    assert np.all(np.abs(sp - part) <= 1e-11 * sabs_p)
+    # the axes matter here: the transposed grid gives a different sum
+    other = oracle.ahc(m.t, m.R, (2, 3, 4), ef, eta, kT)
+    assert np.max(np.abs(other - s)) > 1e-6 * np.max(sabs)
+
+
 # ---------------------------------------------------------------------------
 # Reference gradient
 # ---------------------------------------------------------------------------
