@@ -89,6 +89,8 @@ typedef struct {
                                     kernels (ignored while KUBO_F_GRAPH replays) */
 #define KUBO_F_FORWARD_ONLY 0x4u /* size the workspace for kubo_ahc only; kubo_ahc_backward
                                     then returns KUBO_E_INVALID */
+#define KUBO_F_TENSOR 0x8u       /* size the workspace for kubo_ahc_tensor as well (a third
+                                    set of partial Bloch sums, four result components) */
 #define KUBO_F_DEBUG_SWEEPCAP 0x100u /* cap the iterative eigensolver at one iteration (one
                                     sweep) and route every k-point through it, so that the
                                     device status reports KUBO_E_NOCONV (tests of that path) */
@@ -134,6 +136,30 @@ kubo_status kubo_ahc(kubo_plan_t plan, const double* t, const double* e_fermi, d
                      void* stream);
 
 /*
+ * kubo_ahc_tensor -- the general response of the paper's Eq. (1) for other pairs
+ * of current operators, in one pass (one eigendecomposition per k-point): the
+ * anomalous Hall tensor and the spin Hall conductivity.  For the operator pair
+ * (P, Q) with P' = U^+ P U, Q' = U^+ Q U:
+ *   sigma_PQ[j] = -(1/N_k) sum_k sum_n f(E_n; E_F[j]) Omega^PQ_n,
+ *   Omega^PQ_n  = -2 sum_{m != n} Im(P'_nm Q'_mn) g(E_n - E_m)
+ * (Eq. (3) with its two current operators replaced), for the four pairs
+ *   c = 0: (v_x, v_y) = sigma_xy (equal to kubo_ahc's result, bit for bit)
+ *   c = 1: (v_y, v_z) = sigma_yz      c = 2: (v_z, v_x) = sigma_zx
+ *   c = 3: (Js_x, v_y), the spin Hall conductivity, with the spin current
+ *          Js_x = (s_z v_x + v_x s_z)/2 and s_z = diag(spin) in the orbital basis
+ *          (spin in the caller's units, e.g. +1/-1 for up/down)
+ * v_z = sum_R i R_z t(R) e^{ik.R} (Hermitian part), like v_x and v_y.
+ *   t, e_fermi, eta, kT, workspace as for kubo_ahc
+ *   spin       device, double [sum of n_orb over the models] (the models' orbitals in
+ *              plan order), or NULL: then component 3 is zero and not computed
+ *   sigma      device, double [n_models][4][n_fermi], overwritten
+ * The plan must carry KUBO_F_TENSOR (else KUBO_E_INVALID).  Errors: as kubo_ahc.
+ */
+kubo_status kubo_ahc_tensor(kubo_plan_t plan, const double* t, const double* e_fermi, double eta,
+                            double kT, const double* spin, double* sigma, void* workspace,
+                            size_t workspace_bytes, void* stream);
+
+/*
  * kubo_ahc_backward -- gradient of L = sum_{m,j} sigma_bar[m][j] sigma[m][j]
  * with respect to every hopping: grad_t = dL/dRe t + i dL/dIm t (the
  * convention of complex autograd), by reverse-mode differentiation through
@@ -167,7 +193,7 @@ const char* kubo_status_string(kubo_status status);
  * kubo_plan_kernel_time -- device time of the per-k kernels recorded under
  * KUBO_F_TIMING since the last reset.  which = 0: the forward per-k kernel
  * (Bloch sum, eigensolve, rotation, curvature and Fermi sums); which = 1: the
- * backward per-k kernel.  Waits for the recorded events.  Outputs (each may
+ * backward per-k kernel; which = 2: the per-k kernel of kubo_ahc_tensor.  Waits for the recorded events.  Outputs (each may
  * be NULL): total_ms, the number of launches, and the k-points they covered.
  * reset != 0 forgets the records afterwards.  KUBO_E_INVALID for a NULL plan
  * or a bad which; KUBO_E_HIP if an event query fails.

@@ -7,6 +7,7 @@
 //   k_pencil     sum factorisation of the Bloch sum over one kx pencil:
 //                T_rho  = sum_{R: R_x = rho} t'(R) e^{i(k1 R_y + k2 R_z)}
 //                Ty_rho = sum_{R: R_x = rho} i R_y t'(R) e^{i(k1 R_y + k2 R_z)}
+//                (and, for the Hall tensor, Tz_rho with i R_z likewise)
 //   per-k kernels (kubo_wave.hip for n <= 32, kubo_wg.hip for larger n and for
 //                the adjoint): H = sum_rho e^{i k0 rho} T_rho,
 //                v_x = sum_rho i rho e^{i k0 rho} T_rho, v_y = sum_rho e^{i k0 rho} Ty_rho
@@ -15,6 +16,8 @@
 //                Omega_n = -2 sum_m Im(A_nm B_mn) g(E_n - E_m) and the Fermi-weighted
 //                sums s_j = sum_n f_j(E_n) Omega_n accumulated per k-block (step 4).
 //   k_reduce     sigma_j = -(1/N_k) sum over the model's k-blocks, fixed tree order.
+// The Hall tensor variant of the per-k kernels also rotates v_z and the spin
+// current into the eigenbasis and accumulates four components per level.
 //   k_gacc, k_gsym  the adjoint's transposed Bloch sum and Hermitian-projection rule.
 // All arithmetic is FP64.
 #include <hip/hip_runtime.h>
@@ -79,7 +82,7 @@ constexpr int kPencilPhaseTile = 512;
 
 __global__ __launch_bounds__(kPencilThreads) void k_pencil(Tables tb, int item_begin,
                                                            const double2* __restrict__ tp,
-                                                           double2* __restrict__ tbuf) {
+                                                           double2* __restrict__ tbuf, bool with_z) {
     __shared__ double2 sph[kPencilPhaseTile];
     const PencilItem it = tb.pencils[item_begin + blockIdx.x];
     const ModelDev md = tb.models[it.model];
@@ -87,14 +90,15 @@ __global__ __launch_bounds__(kPencilThreads) void k_pencil(Tables tb, int item_b
     const long long nn = (long long)n * n;
     double2* T0 = tbuf + it.tbuf_off;
     double2* T1 = T0 + (long long)md.nR0 * nn;
+    double2* T2 = T1 + (long long)md.nR0 * nn;
     const int* gstart = tb.grp_start + md.gs_first;
     for (int rho = 0; rho < md.nR0; ++rho) {
         const int g0 = gstart[rho], g1 = gstart[rho + 1];
         // elements handled by this thread: e = tid, tid + NT, ...  (accumulate over R tiles)
         for (long long e0 = 0; e0 < nn; e0 += kPencilThreads * 4) {
-            double2 a0[4], a1[4];
+            double2 a0[4], a1[4], a2[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) a0[u] = a1[u] = c_make(0.0, 0.0);
+            for (int u = 0; u < 4; ++u) a0[u] = a1[u] = a2[u] = c_make(0.0, 0.0);
             for (int gt = g0; gt < g1; gt += kPencilPhaseTile) {
                 const int gcount = min(kPencilPhaseTile, g1 - gt);
                 __syncthreads();
@@ -110,6 +114,7 @@ __global__ __launch_bounds__(kPencilThreads) void k_pencil(Tables tb, int item_b
                     const double ry = (double)tb.grp_R1[gi];
                     const double2 ph = sph[g];
                     const double2 phy = c_i(c_scale(ry, ph));
+                    const double2 phz = c_i(c_scale((double)tb.grp_R2[gi], ph));
                     const double2* tr = tp + md.t_off + (long long)r * nn;
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
@@ -118,6 +123,7 @@ __global__ __launch_bounds__(kPencilThreads) void k_pencil(Tables tb, int item_b
                             double2 v = tr[e];
                             a0[u] = c_fma(v, ph, a0[u]);
                             a1[u] = c_fma(v, phy, a1[u]);
+                            if (with_z) a2[u] = c_fma(v, phz, a2[u]);
                         }
                     }
                 }
@@ -128,6 +134,7 @@ __global__ __launch_bounds__(kPencilThreads) void k_pencil(Tables tb, int item_b
                 if (e < nn) {
                     T0[(long long)rho * nn + e] = a0[u];
                     T1[(long long)rho * nn + e] = a1[u];
+                    if (with_z) T2[(long long)rho * nn + e] = a2[u];
                 }
             }
         }
@@ -249,7 +256,7 @@ __global__ void k_gsym(Tables tb, int n_models, long long total, double2* __rest
 // k_reduce: sigma[model][j] = -(1/N_k) sum_slots partial[slot][j], fixed order
 // ---------------------------------------------------------------------------
 constexpr int kReduceThreads = 256;
-__global__ __launch_bounds__(kReduceThreads) void k_reduce(Tables tb, int nF,
+__global__ __launch_bounds__(kReduceThreads) void k_reduce(Tables tb, int nF, int ncomp,
                                                            const double* __restrict__ partial,
                                                            double* __restrict__ sigma,
                                                            unsigned* status) {
@@ -258,8 +265,9 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(Tables tb, int nF,
     const int j = blockIdx.x;
     const ModelDev md = tb.models[m];
     double s = 0.0;
+    const int w = nF * ncomp;  // j runs over the components' levels, [ncomp][nF]
     for (int k = threadIdx.x; k < md.slot_count; k += kReduceThreads)
-        s += partial[(long long)(md.slot_first + k) * nF + j];
+        s += partial[(long long)(md.slot_first + k) * w + j];
     red[threadIdx.x] = s;
     __syncthreads();
     for (int w = kReduceThreads / 2; w > 0; w >>= 1) {
@@ -269,7 +277,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(Tables tb, int nF,
     if (threadIdx.x == 0) {
         const double v = -red[0] / (double)md.Nk;
         if (!isfinite(v)) atomicOr(status, kStatNonFinite);
-        sigma[md.f_off + j] = v;
+        sigma[(long long)md.f_off * ncomp + j] = v;
     }
 }
 
@@ -382,10 +390,11 @@ __global__ __launch_bounds__(kPaccThreads) void k_pacc(Tables tb, int begin, con
 }
 
 hipError_t launch_pencil(const Tables& tb, int item_begin, int item_count, const double* tp,
-                         double* tbuf, hipStream_t s) {
+                         double* tbuf, bool with_z, hipStream_t s) {
     if (item_count <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_pencil, dim3(item_count), dim3(kPencilThreads), 0, s, tb, item_begin,
-                       reinterpret_cast<const double2*>(tp), reinterpret_cast<double2*>(tbuf));
+                       reinterpret_cast<const double2*>(tp), reinterpret_cast<double2*>(tbuf),
+                       with_z);
     return hipGetLastError();
 }
 
@@ -420,10 +429,10 @@ hipError_t launch_gsym(const Tables& tb, int n_models, long long total, double* 
     return hipGetLastError();
 }
 
-hipError_t launch_reduce(const Tables& tb, int n_models, int nF, const double* partial,
+hipError_t launch_reduce(const Tables& tb, int n_models, int nF, int ncomp, const double* partial,
                          double* sigma, unsigned* status, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce, dim3(nF, n_models), dim3(kReduceThreads), 0, s, tb, nF, partial,
-                       sigma, status);
+    hipLaunchKernelGGL(k_reduce, dim3(nF * ncomp, n_models), dim3(kReduceThreads), 0, s, tb, nF,
+                       ncomp, partial, sigma, status);
     return hipGetLastError();
 }
 

@@ -98,6 +98,7 @@ struct kubo_plan_s {
         size_t tab_pencils = 0, tab_blocks = 0, tab_granges = 0;
     } fwd, bwd;
     int n_slots = 0;
+    int n_orb_total = 0;    // orbitals summed over the models (length of a spin array)
     long long t_elems = 0;  // complex elements of t (all models)
     // workspace layout
     size_t off_tables = 0, off_tp = 0, off_tbuf = 0, off_pbuf = 0, off_xbuf = 0, off_partial = 0,
@@ -109,7 +110,7 @@ struct kubo_plan_s {
     size_t tab_off[10] = {0};
     unsigned long long id = 0;           // unique per plan (never reused)
     std::set<const void*> used_ws;       // workspaces this plan has run on
-    CachedGraph graph_fwd, graph_bwd;
+    CachedGraph graph_fwd, graph_bwd, graph_tensor;
     int max_groups = 2048;
     int max_group = 1;  // most lattice vectors sharing one R_x value
     // KUBO_F_TIMING: event pairs around per-k kernel launches
@@ -161,13 +162,19 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
     const size_t cap = chunk_cap_bytes();
 
     long long t_off = 0;
+    int orb_off = 0;
     int slot = 0;
+    const bool tensor = (flags & KUBO_F_TENSOR) != 0;
+    // pencil partial sets per pencil: T and Ty, and Tz for the Hall tensor
+    const int nsets = tensor ? 3 : 2;
+    const int ncomp = tensor ? 4 : 1;
     // per model: tables and its pencils / blocks (in model order)
     struct PB {
         PencilItem pi;
         std::vector<BlockItem> blocks;   // forward k-blocks (the tile's k_block)
         std::vector<BlockItem> bblocks;  // backward k-blocks: longer, so fewer pencil partials
         size_t tbytes, pbytes;
+        size_t pmat;    // backward: one k-block's pencil partials (bytes)
         size_t xbytes;  // backward, one-wavefront classes: the per-k adjoint matrices
         int cls;
     };
@@ -183,6 +190,8 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
         md.t_off = t_off;
         md.Nk = (long long)d.grid[0] * d.grid[1] * d.grid[2];
         md.f_off = m * nF;
+        md.orb_off = orb_off;
+        orb_off += d.n_orb;
         // distinct R_x values, ascending, and R grouped by them
         std::vector<int> xs;
         for (int r = 0; r < d.n_R; ++r) xs.push_back(d.R[3 * r]);
@@ -238,7 +247,8 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
         }
         md.slot_first = slot;
         const long long nn = (long long)d.n_orb * d.n_orb;
-        const size_t mat_bytes = (size_t)2 * md.nR0 * nn * 16;
+        const size_t mat_bytes = (size_t)2 * md.nR0 * nn * 16;  // per backward k-block
+        const size_t tset_bytes = (size_t)nsets * md.nR0 * nn * 16;  // per pencil
         if (kc > 0) {
             for (long long pc = kb / d.grid[0]; pc <= (ke - 1) / d.grid[0]; ++pc) {
                 PB pb;
@@ -247,7 +257,8 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
                 pb.pi.i2 = (int)(pc / d.grid[1]);
                 pb.pi.pad = 0;
                 pb.pi.tbuf_off = 0;
-                pb.tbytes = mat_bytes;
+                pb.tbytes = tset_bytes;
+                pb.pmat = mat_bytes;
                 pb.cls = cls;
                 long long a0 = std::max(kb - pc * d.grid[0], 0LL);
                 long long a1 = std::min(ke - pc * d.grid[0], (long long)d.grid[0]);
@@ -345,7 +356,7 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
             pi.tbuf_off = (long long)(cur.tbytes / 16);
             long long poff = (long long)(cur.pbytes / 16);
             long long xoff = (long long)(cur.xbytes / 16);
-            const long long mat = (long long)(pb.tbytes / 16);
+            const long long mat = (long long)(pb.pmat / 16);
             const long long nn = (long long)models[pi.model].n_orb * models[pi.model].n_orb;
             for (auto& b : (with_p ? pb.bblocks : pb.blocks)) {
                 b.tbuf_off = pi.tbuf_off;
@@ -400,7 +411,8 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
     P->off_xbuf = off;
     if (!(P->flags & KUBO_F_FORWARD_ONLY)) off = align_up(off + P->bwd.max_x);
     P->off_partial = off;
-    off = align_up(off + (size_t)P->n_slots * nF * 8);
+    off = align_up(off + (size_t)P->n_slots * nF * ncomp * 8);
+    P->n_orb_total = orb_off;
     {
         int nmax = 1;
         for (const auto& md : P->models) nmax = std::max(nmax, md.n);
@@ -429,7 +441,8 @@ kubo_status validate(const kubo_model_desc* models, int n_models, int nF, uint32
                      const kubo_tile* tiles, int n_tiles) {
     if (!models || n_models < 1) return KUBO_E_INVALID;
     if (nF < 1 || nF > kMaxFermi) return KUBO_E_INVALID;
-    if (flags & ~(KUBO_F_GRAPH | KUBO_F_TIMING | KUBO_F_FORWARD_ONLY | KUBO_F_DEBUG_SWEEPCAP))
+    if (flags & ~(KUBO_F_GRAPH | KUBO_F_TIMING | KUBO_F_FORWARD_ONLY | KUBO_F_TENSOR |
+                  KUBO_F_DEBUG_SWEEPCAP))
         return KUBO_E_INVALID;
     if (n_tiles < 0 || (n_tiles > 0 && !tiles)) return KUBO_E_INVALID;
     for (int i = 0; i < n_tiles; ++i) {
@@ -536,7 +549,8 @@ struct TimedScope {
 };
 
 kubo_status enqueue_forward(kubo_plan_s* P, const double* t, const double* ef, double eta,
-                            double kT, double* sigma, unsigned char* ws, hipStream_t s) {
+                            double kT, double* sigma, unsigned char* ws, hipStream_t s,
+                            bool tensor = false, const double* spin = nullptr) {
     const Tables tb = device_tables(P, ws, false);
     unsigned* status = reinterpret_cast<unsigned*>(ws);
     double* tp = reinterpret_cast<double*>(ws + P->off_tp);
@@ -547,10 +561,10 @@ kubo_status enqueue_forward(kubo_plan_s* P, const double* t, const double* ef, d
     HIP_TRY(launch_clear(status, s));
     HIP_TRY(launch_hermproj(tb, P->n_models, P->t_elems, t, tp, s));
     for (const Chunk& c : P->fwd.chunks) {
-        HIP_TRY(launch_pencil(tb, c.pencil_begin, c.pencil_count, tp, tbuf, s));
+        HIP_TRY(launch_pencil(tb, c.pencil_begin, c.pencil_count, tp, tbuf, tensor, s));
         for (int k = 0; k < kNumClasses; ++k) {
             if (c.cls[k].count == 0) continue;
-            TimedScope ts(P, s, 0, c.cls_kpts[k]);
+            TimedScope ts(P, s, tensor ? 2 : 0, c.cls_kpts[k]);
             if (kClasses[k].wave) {
                 FwdLaunch L;
                 L.tb = tb;
@@ -566,6 +580,8 @@ kubo_status enqueue_forward(kubo_plan_s* P, const double* t, const double* ef, d
                 L.item_count = c.cls[k].count;
                 L.np = kClasses[k].np;
                 L.max_groups = P->max_groups;
+                L.tensor = tensor ? 1 : 0;
+                L.spin = spin;
                 HIP_TRY(launch_forward_wave(L, s));
             } else {
                 WgLaunch L{};
@@ -585,12 +601,14 @@ kubo_status enqueue_forward(kubo_plan_s* P, const double* t, const double* ef, d
                 L.item_begin = c.cls[k].begin;
                 L.item_count = c.cls[k].count;
                 L.max_groups = P->wg_groups;
+                L.tensor = tensor ? 1 : 0;
+                L.spin = spin;
                 HIP_TRY(launch_forward_wg(L, kClasses[k].np, s));
             }
             ts.finish();
         }
     }
-    HIP_TRY(launch_reduce(tb, P->n_models, P->nF, partial, sigma, status, s));
+    HIP_TRY(launch_reduce(tb, P->n_models, P->nF, tensor ? 4 : 1, partial, sigma, status, s));
     return KUBO_OK;
 }
 
@@ -609,7 +627,7 @@ kubo_status enqueue_backward(kubo_plan_s* P, const double* t, const double* ef, 
     HIP_TRY(launch_hermproj(tb, P->n_models, P->t_elems, t, tp, s));
     HIP_TRY(launch_zero(grad, 2 * P->t_elems, s));
     for (const Chunk& c : P->bwd.chunks) {
-        HIP_TRY(launch_pencil(tb, c.pencil_begin, c.pencil_count, tp, tbuf, s));
+        HIP_TRY(launch_pencil(tb, c.pencil_begin, c.pencil_count, tp, tbuf, false, s));
         for (int k = 0; k < kNumClasses; ++k) {
             if (c.cls[k].count == 0) continue;
             WgLaunch L{};
@@ -690,9 +708,10 @@ namespace kubo {
 
 kubo_status ahc_enqueue(kubo_plan_s* plan, const double* t, const double* e_fermi, double eta,
                         double kT, double* sigma, void* workspace, size_t workspace_bytes,
-                        void* stream, bool allow_graph) {
+                        void* stream, bool allow_graph, bool tensor, const double* spin) {
     if (!plan || !t || !e_fermi || !sigma) return KUBO_E_INVALID;
     if (!finite_nonneg(eta) || !finite_nonneg(kT)) return KUBO_E_INVALID;
+    if (tensor && !(plan->flags & KUBO_F_TENSOR)) return KUBO_E_INVALID;
     if (!workspace || workspace_bytes < plan->total) return KUBO_E_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     unsigned char* ws = static_cast<unsigned char*>(workspace);
@@ -704,21 +723,22 @@ kubo_status ahc_enqueue(kubo_plan_s* plan, const double* t, const double* e_ferm
         key.p[1] = e_fermi;
         key.p[2] = sigma;
         key.p[3] = workspace;
+        key.p[5] = spin;
         key.d[0] = eta;
         key.d[1] = kT;
         key.stream = stream;
-        return run_graph(plan, plan->graph_fwd, key, s, [&]() {
-            return enqueue_forward(plan, t, e_fermi, eta, kT, sigma, ws, s);
+        return run_graph(plan, tensor ? plan->graph_tensor : plan->graph_fwd, key, s, [&]() {
+            return enqueue_forward(plan, t, e_fermi, eta, kT, sigma, ws, s, tensor, spin);
         });
     }
     if (!allow_graph) {
         // no event records either: the caller may not be able to create them
         plan->no_events = true;
-        st = enqueue_forward(plan, t, e_fermi, eta, kT, sigma, ws, s);
+        st = enqueue_forward(plan, t, e_fermi, eta, kT, sigma, ws, s, tensor, spin);
         plan->no_events = false;
         return st;
     }
-    return enqueue_forward(plan, t, e_fermi, eta, kT, sigma, ws, s);
+    return enqueue_forward(plan, t, e_fermi, eta, kT, sigma, ws, s, tensor, spin);
 }
 
 }  // namespace kubo
@@ -752,6 +772,13 @@ kubo_status kubo_ahc(kubo_plan_t plan, const double* t, const double* e_fermi, d
                      void* stream) {
     return kubo::ahc_enqueue(plan, t, e_fermi, eta, kT, sigma, workspace, workspace_bytes, stream,
                              true);
+}
+
+kubo_status kubo_ahc_tensor(kubo_plan_t plan, const double* t, const double* e_fermi, double eta,
+                            double kT, const double* spin, double* sigma, void* workspace,
+                            size_t workspace_bytes, void* stream) {
+    return kubo::ahc_enqueue(plan, t, e_fermi, eta, kT, sigma, workspace, workspace_bytes, stream,
+                             true, true, spin);
 }
 
 kubo_status kubo_ahc_backward(kubo_plan_t plan, const double* t, const double* e_fermi,
@@ -795,7 +822,7 @@ kubo_status kubo_plan_device_status(kubo_plan_t plan, const void* workspace, voi
 
 kubo_status kubo_plan_kernel_time(kubo_plan_t plan, int32_t which, double* total_ms,
                                   int64_t* launches, int64_t* k_points, int32_t reset) {
-    if (!plan || which < 0 || which > 1) return KUBO_E_INVALID;
+    if (!plan || which < 0 || which > 2) return KUBO_E_INVALID;
     double ms = 0.0;
     long long nl = 0, kp = 0;
     for (const auto& r : plan->trec) {
@@ -833,7 +860,7 @@ void kubo_plan_destroy(kubo_plan_t plan) {
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);
     }
-    for (CachedGraph* g : {&plan->graph_fwd, &plan->graph_bwd}) {
+    for (CachedGraph* g : {&plan->graph_fwd, &plan->graph_bwd, &plan->graph_tensor}) {
         if (g->exec) (void)hipGraphExecDestroy(g->exec);
         if (g->graph) (void)hipGraphDestroy(g->graph);
     }

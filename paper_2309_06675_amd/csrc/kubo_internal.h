@@ -26,7 +26,7 @@ struct ModelDev {
     int f_off;       // offset of this model in e_fermi / sigma (model * n_fermi)
     int slot_first;  // first partial-sum slot (k-block) of the model
     int slot_count;  // number of slots
-    int pad0;
+    int orb_off;     // offset of this model's orbitals in a per-orbital array (spin)
     long long t_off; // offset (complex elements) of the model in t / t' / grad_t
     long long Nk;    // full grid size (normaliser)
 };

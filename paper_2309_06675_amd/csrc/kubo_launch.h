@@ -20,6 +20,11 @@ struct FwdLaunch {
     int item_begin, item_count;
     int np;          // padded size class of every item in the list
     int max_groups;  // persistent grid size cap
+    // Hall tensor (tensor != 0): the pencil partials hold a third set (the i R_z sums), the
+    // partial sums four components per slot ([slot][4][nF]: xy, yz, zx, spin Hall), and
+    // spin (per orbital, all models; NULL: no spin Hall component) weights the spin current
+    int tensor;
+    const double* spin;
 };
 
 struct WgLaunch {
@@ -38,6 +43,8 @@ struct WgLaunch {
     int max_iter;
     int item_begin, item_count;
     int max_groups;
+    int tensor;           // forward only: as FwdLaunch::tensor
+    const double* spin;   // forward only: as FwdLaunch::spin
 };
 
 long long wg_slot_elems(int nmax);
@@ -51,8 +58,9 @@ hipError_t launch_clear(unsigned* status, hipStream_t s);
 hipError_t launch_zero(double* p, long long count, hipStream_t s);
 hipError_t launch_hermproj(const Tables& tb, int n_models, long long total, const double* t,
                            double* tp, hipStream_t s);
+// with_z: also the i R_z-weighted partial sums (third set, for the Hall tensor)
 hipError_t launch_pencil(const Tables& tb, int item_begin, int item_count, const double* tp,
-                         double* tbuf, hipStream_t s);
+                         double* tbuf, bool with_z, hipStream_t s);
 hipError_t launch_forward_wave(const FwdLaunch& L, hipStream_t s);
 // pencil sums of the adjoint matrices of blocks [begin, begin + count):
 // PH_rho = sum_k e^{-i k0 rho}(Hbar - i rho vbar_x), PY_rho = sum_k e^{-i k0 rho} vbar_y
@@ -64,13 +72,16 @@ hipError_t launch_gacc(const Tables& tb, const GaccRange* ranges, int range_begi
                        hipStream_t s);
 hipError_t launch_gsym(const Tables& tb, int n_models, long long total, double* grad,
                        hipStream_t s);
-hipError_t launch_reduce(const Tables& tb, int n_models, int nF, const double* partial,
+// ncomp components per slot and per model: partial [slot][ncomp * nF], sigma
+// [model][ncomp * nF]
+hipError_t launch_reduce(const Tables& tb, int n_models, int nF, int ncomp, const double* partial,
                          double* sigma, unsigned* status, hipStream_t s);
 
 // The body of kubo_ahc on a given workspace.  allow_graph = false: eager
 // launches only, and no timing events (the no-allocation entry point).
 kubo_status ahc_enqueue(kubo_plan_t plan, const double* t, const double* e_fermi, double eta,
                         double kT, double* sigma, void* workspace, size_t workspace_bytes,
-                        void* stream, bool allow_graph);
+                        void* stream, bool allow_graph, bool tensor = false,
+                        const double* spin = nullptr);
 
 }  // namespace kubo

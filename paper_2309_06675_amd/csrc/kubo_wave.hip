@@ -621,7 +621,8 @@ __device__ __forceinline__ void upper_index(int e, int& i, int& j) {
 // coef = e^{i k0 rho} (times i rho for v_x).  W = v U passes through S.P.
 template <int NP>
 __device__ void wave_velocity(WaveLds<NP>& S, int n, int nR0, const double2* __restrict__ T,
-                              const int* __restrict__ r0, bool is_x, double2 (&M)[NP / 2]) {
+                              const int* __restrict__ r0, bool is_x, double2 (&M)[NP / 2],
+                              const double* sw = nullptr) {
     constexpr int LD = WaveLds<NP>::LD;
     constexpr int HW = NP / 2;
     const int lane = threadIdx.x & 63;
@@ -639,6 +640,7 @@ __device__ void wave_velocity(WaveLds<NP>& S, int n, int nR0, const double2* __r
                 if (is_x) cf = c_scale((double)r0[rho], c_i(cf));
                 v = c_fma(cf, T[(long long)rho * nn + i * n + l], v);
             }
+            if (sw) v = c_scale(0.5 * (sw[i] + sw[l]), v);  // spin current (s v + v s)/2
 #pragma unroll
             for (int jj = 0; jj < HW; ++jj) acc[jj] = c_fma(v, S.U[l * LD + j0 + jj], acc[jj]);
         }
@@ -672,7 +674,8 @@ __device__ void wave_velocity(WaveLds<NP>& S, int n, int nR0, const double2* __r
 // consecutive elements of a row, so the loads stay coalesced.
 template <int NP>
 __device__ void wave_stage_velocity(WaveLds<NP>& S, int n, int nR0, const double2* __restrict__ T,
-                                    const int* __restrict__ r0, bool is_x) {
+                                    const int* __restrict__ r0, bool is_x,
+                                    const double* sw = nullptr) {
     constexpr int LD = WaveLds<NP>::LD;
     constexpr int NU = NP * (NP + 1) / 2;
     constexpr int PER = (NU + 63) / 64;
@@ -704,6 +707,8 @@ __device__ void wave_stage_velocity(WaveLds<NP>& S, int n, int nR0, const double
             upper_index<NP>(e, i, j);
             double2 v = acc[q];
             if (i == j) v.y = 0.0;
+            // spin current (s v + v s)/2 for a diagonal s (zero past n: v is zero there)
+            if (sw && j < n) v = c_scale(0.5 * (sw[i] + sw[j]), v);
             S.P[i * LD + j] = v;
             S.P[j * LD + i] = c_conj(v);
         }
@@ -802,7 +807,8 @@ __device__ void wave_rotate_mfma(const WaveLds<NP>& S, const double2 (&u)[NP / 1
 template <int NP>
 __device__ void wave_curvature_mfma(WaveLds<NP>& S, int n, double eta2,
                                     const v4d (&ar)[NP / 16][NP / 16], const v4d (&ai)[NP / 16][NP / 16],
-                                    const v4d (&br)[NP / 16][NP / 16], const v4d (&bi)[NP / 16][NP / 16]) {
+                                    const v4d (&br)[NP / 16][NP / 16], const v4d (&bi)[NP / 16][NP / 16],
+                                    double* out) {
     constexpr int NT = NP / 16;
     const int lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
     double om[NT][4];
@@ -835,7 +841,73 @@ __device__ void wave_curvature_mfma(WaveLds<NP>& S, int n, double eta2,
         for (int q = 0; q < 4; ++q) {
             const double tot = row16_sum(om[ti][q]);
             const int i = 16 * ti + g + 4 * q;
-            if (c16 == 0 && i < n) S.Om[i] = -2.0 * tot;
+            if (c16 == 0 && i < n) out[i] = -2.0 * tot;
+        }
+}
+
+// The Hall tensor's extra LDS, placed right after WaveLds: the curvatures of the
+// yz, zx and spin Hall pairs, and the spin diagonal of the k-point's model.
+template <int NP>
+struct WaveTensorLds {
+    double Om2[3][NP];
+    double spin[NP];
+};
+
+// An accumulator-layout matrix (element q of tile (ti, tj) is M[16 ti + g + 4 q][16 tj + c])
+// written out in full to an LDS matrix with leading dimension LD.
+template <int NP>
+__device__ void wave_store_acc(double2* M, const v4d (&mr)[NP / 16][NP / 16],
+                               const v4d (&mi)[NP / 16][NP / 16]) {
+    constexpr int LD = WaveLds<NP>::LD, NT = NP / 16;
+    const int lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                M[(16 * ti + g + 4 * q) * LD + 16 * tj + c16] = c_make(mr[ti][tj][q], mi[ti][tj][q]);
+}
+
+// out_i = -2 sum_{j != i} Im(P_ij conj(Q_ij)) g(E_i - E_j) with P in accumulator tiles
+// and Q (Hermitian) read from the LDS matrix Qm at the same positions.
+template <int NP>
+__device__ void wave_curvature_lds(WaveLds<NP>& S, int n, double eta2,
+                                   const v4d (&pr)[NP / 16][NP / 16], const v4d (&pi)[NP / 16][NP / 16],
+                                   const double2* Qm, double* out) {
+    constexpr int LD = WaveLds<NP>::LD, NT = NP / 16;
+    const int lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
+    double om[NT][4];
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) om[ti][q] = 0.0;
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj) {
+        const int j = 16 * tj + c16;
+        const double ej = (j < n) ? S.E[j] : 0.0;
+#pragma unroll
+        for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = 16 * ti + g + 4 * q;
+                if (i < n && j < n && i != j) {
+                    const double de = S.E[i] - ej;
+                    const double den = de * de + eta2;
+                    if (den > 0.0) {
+                        const double2 qv = Qm[i * LD + j];
+                        om[ti][q] += (pi[ti][tj][q] * qv.x - pr[ti][tj][q] * qv.y) / den;
+                    }
+                }
+            }
+    }
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double tot = row16_sum(om[ti][q]);
+            const int i = 16 * ti + g + 4 * q;
+            if (c16 == 0 && i < n) out[i] = -2.0 * tot;
         }
 }
 
@@ -980,19 +1052,25 @@ __device__ bool wave_eigen(WaveLds<NP>& S, const ModelDev& md, const double2* __
 }
 
 // ---------------------------------------------------------------------------
-// k_forward_wave: steps 1-4 with one wavefront per workgroup (n <= NP <= 32)
+// k_forward_wave: steps 1-4 with one wavefront per workgroup (n <= NP <= 32).
+// TENSOR: also v_z and the spin current (s v_x + v_x s)/2 rotated into the
+// eigenbasis, four curvatures per band (pairs (v_x, v_y), (v_y, v_z), (v_z, v_x),
+// (Js_x, v_y)) and four Fermi sums per level.
 // ---------------------------------------------------------------------------
-template <int NP>
+template <int NP, bool TENSOR>
 __global__ __launch_bounds__(64) void k_forward_wave(FwdLaunch a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     WaveLds<NP>& S = *reinterpret_cast<WaveLds<NP>*>(smem_raw);
+    WaveTensorLds<NP>& ST = *reinterpret_cast<WaveTensorLds<NP>*>(smem_raw + sizeof(WaveLds<NP>));
     constexpr int LD = WaveLds<NP>::LD;
     constexpr int HW = NP / 2;
     constexpr int NT = NP / 16;
+    constexpr int NC = TENSOR ? 4 : 1;
     const int lane = threadIdx.x & 63;
     const double eta2 = a.eta * a.eta;
     const int max_iter = a.max_sweeps >= kMaxSweeps ? 30 : 1;
     const double2* tbuf = reinterpret_cast<const double2*>(a.tbuf);
+    const bool with_spin = TENSOR && a.spin != nullptr;
     // U's padding (rows and columns n..NP-1) is never written below: keep it finite
     for (int e = lane; e < NP * LD; e += 64) S.U[e] = c_make(0.0, 0.0);
     __syncthreads();
@@ -1004,9 +1082,18 @@ __global__ __launch_bounds__(64) void k_forward_wave(FwdLaunch a) {
         const long long nn = (long long)n * n;
         const double2* T0 = tbuf + it.tbuf_off;
         const double2* T1 = T0 + (long long)md.nR0 * nn;
+        const double2* T2 = T1 + (long long)md.nR0 * nn;
         const int* r0 = a.tb.r0val + md.r0_first;
         const double* ef = a.e_fermi + md.f_off;
-        double* part = a.partial + (long long)it.slot * a.nF;
+        double* part = a.partial + (long long)it.slot * a.nF * NC;
+        if constexpr (TENSOR) {
+            if (lane < NP) ST.spin[lane] = (with_spin && lane < n) ? a.spin[md.orb_off + lane] : 0.0;
+            if (lane < NP) {
+                ST.Om2[0][lane] = 0.0;
+                ST.Om2[1][lane] = 0.0;
+                ST.Om2[2][lane] = 0.0;
+            }
+        }
         for (int kk = 0; kk < it.count; ++kk) {
             bool vx_in_p;
             const bool ok = wave_eigen<NP>(S, md, T0, r0, it.i0 + kk, max_iter, vx_in_p);
@@ -1025,41 +1112,84 @@ __global__ __launch_bounds__(64) void k_forward_wave(FwdLaunch a) {
                 wave_stage_velocity<NP>(S, n, md.nR0, T1, r0, false);
                 __syncthreads();
                 wave_rotate_mfma<NP>(S, u, br, bi);
-                wave_curvature_mfma<NP>(S, n, eta2, ar, ai, br, bi);
+                wave_curvature_mfma<NP>(S, n, eta2, ar, ai, br, bi, S.Om);
+                if constexpr (TENSOR) {
+                    // U sits in registers now: S.U keeps A for the (v_z, v_x) pair
+                    wave_store_acc<NP>(S.U, ar, ai);
+                    if (with_spin) {
+                        __syncthreads();
+                        wave_stage_velocity<NP>(S, n, md.nR0, T0, r0, true, ST.spin);
+                        __syncthreads();
+                        wave_rotate_mfma<NP>(S, u, ar, ai);  // D = U^+ Js_x U
+                        wave_curvature_mfma<NP>(S, n, eta2, ar, ai, br, bi, ST.Om2[2]);
+                    }
+                    __syncthreads();
+                    wave_stage_velocity<NP>(S, n, md.nR0, T2, r0, false);
+                    __syncthreads();
+                    wave_rotate_mfma<NP>(S, u, ar, ai);  // C = U^+ v_z U
+                    wave_curvature_mfma<NP>(S, n, eta2, br, bi, ar, ai, ST.Om2[0]);
+                    wave_curvature_lds<NP>(S, n, eta2, ar, ai, S.U, ST.Om2[1]);
+                }
             } else {
                 double2 Ma[HW], Mb[HW];
                 wave_velocity<NP>(S, n, md.nR0, T0, r0, true, Ma);
                 wave_velocity<NP>(S, n, md.nR0, T1, r0, false, Mb);
-                // Omega_i = -2 sum_{j != i} Im(A_ij B_ji) g(E_i - E_j), B_ji = conj(B_ij)
+                // Omega_i = -2 sum_{j != i} Im(P_ij Q_ji) g(E_i - E_j), Q_ji = conj(Q_ij)
                 const int i = lane >> 1;
                 const int j0 = (lane & 1) * HW;
-                double om = 0.0;
-                if (i < n) {
-                    const double ei = S.E[i];
+                auto curv = [&](const double2 (&P)[HW], const double2 (&Q)[HW], double* out) {
+                    double om = 0.0;
+                    if (i < n) {
+                        const double ei = S.E[i];
 #pragma unroll
-                    for (int jj = 0; jj < HW; ++jj) {
-                        const int j = j0 + jj;
-                        if (j < n && j != i) {
-                            const double de = ei - S.E[j];
-                            const double den = de * de + eta2;
-                            if (den > 0.0) {
-                                const double q = Ma[jj].y * Mb[jj].x - Ma[jj].x * Mb[jj].y;
-                                om += q / den;
+                        for (int jj = 0; jj < HW; ++jj) {
+                            const int j = j0 + jj;
+                            if (j < n && j != i) {
+                                const double de = ei - S.E[j];
+                                const double den = de * de + eta2;
+                                if (den > 0.0) {
+                                    const double q = P[jj].y * Q[jj].x - P[jj].x * Q[jj].y;
+                                    om += q / den;
+                                }
                             }
                         }
                     }
+                    om += __shfl_xor(om, 1, 64);
+                    if (i < n && (lane & 1) == 0) out[i] = -2.0 * om;
+                };
+                curv(Ma, Mb, S.Om);
+                if constexpr (TENSOR) {
+                    double2 Mc[HW];
+                    wave_velocity<NP>(S, n, md.nR0, T2, r0, false, Mc);
+                    curv(Mb, Mc, ST.Om2[0]);
+                    curv(Mc, Ma, ST.Om2[1]);
+                    if (with_spin) {
+                        wave_velocity<NP>(S, n, md.nR0, T0, r0, true, Mc, ST.spin);
+                        curv(Mc, Mb, ST.Om2[2]);
+                    }
                 }
-                om += __shfl_xor(om, 1, 64);
-                if (i < n && (lane & 1) == 0) S.Om[i] = -2.0 * om;
             }
             __syncthreads();
             const double ikT = (a.kT > 0.0) ? 1.0 / a.kT : 0.0;
             for (int j = lane; j < a.nF; j += 64) {
                 const double efj = ef[j];
-                double s = 0.0;
-                for (int b = 0; b < n; ++b) s += occupation_ikt(S.E[b], efj, a.kT, ikT) * S.Om[b];
-                if (!isfinite(s)) atomicOr(a.status, kStatNonFinite);
-                part[j] = (kk == 0) ? s : part[j] + s;
+                double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+                for (int b = 0; b < n; ++b) {
+                    const double f = occupation_ikt(S.E[b], efj, a.kT, ikT);
+                    s0 += f * S.Om[b];
+                    if constexpr (TENSOR) {
+                        s1 += f * ST.Om2[0][b];
+                        s2 += f * ST.Om2[1][b];
+                        s3 += f * ST.Om2[2][b];
+                    }
+                }
+                if (!isfinite(s0 + s1 + s2 + s3)) atomicOr(a.status, kStatNonFinite);
+                part[j] = (kk == 0) ? s0 : part[j] + s0;
+                if constexpr (TENSOR) {
+                    part[a.nF + j] = (kk == 0) ? s1 : part[a.nF + j] + s1;
+                    part[2 * a.nF + j] = (kk == 0) ? s2 : part[2 * a.nF + j] + s2;
+                    part[3 * a.nF + j] = (kk == 0) ? s3 : part[3 * a.nF + j] + s3;
+                }
             }
             __syncthreads();
         }
@@ -1067,18 +1197,18 @@ __global__ __launch_bounds__(64) void k_forward_wave(FwdLaunch a) {
     (void)LD;
 }
 
-template <int NP>
+template <int NP, bool TENSOR>
 static hipError_t launch_forward_wave_t(const FwdLaunch& L, hipStream_t s) {
-    const size_t lds = sizeof(WaveLds<NP>);
+    const size_t lds = sizeof(WaveLds<NP>) + (TENSOR ? sizeof(WaveTensorLds<NP>) : 0);
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_forward_wave<NP>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_forward_wave<NP, TENSOR>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
     int grid = L.item_count < L.max_groups ? L.item_count : L.max_groups;
-    hipLaunchKernelGGL((k_forward_wave<NP>), dim3(grid), dim3(64), lds, s, L);
+    hipLaunchKernelGGL((k_forward_wave<NP, TENSOR>), dim3(grid), dim3(64), lds, s, L);
     return hipGetLastError();
 }
 
@@ -1086,11 +1216,11 @@ hipError_t launch_forward_wave(const FwdLaunch& L, hipStream_t s) {
     if (L.item_count <= 0) return hipSuccess;
     switch (L.np) {
         case 8:
-            return launch_forward_wave_t<8>(L, s);
+            return L.tensor ? launch_forward_wave_t<8, true>(L, s) : launch_forward_wave_t<8, false>(L, s);
         case 16:
-            return launch_forward_wave_t<16>(L, s);
+            return L.tensor ? launch_forward_wave_t<16, true>(L, s) : launch_forward_wave_t<16, false>(L, s);
         case 32:
-            return launch_forward_wave_t<32>(L, s);
+            return L.tensor ? launch_forward_wave_t<32, true>(L, s) : launch_forward_wave_t<32, false>(L, s);
         default:
             return hipErrorInvalidValue;
     }

@@ -50,6 +50,8 @@ struct WgLds {
     double dphi[kWgMaxN];
     double2 ta[kTile * (kTile + 1)];
     double2 tb[kTile * (kTile + 1)];
+    // Hall tensor: curvatures of the (v_y, v_z), (v_z, v_x), (Js_x, v_y) pairs
+    double Om2[3][kWgMaxN];
 };
 
 // The n <= 64 kernels get 80 KB of LDS per workgroup (two workgroups per CU):
@@ -178,6 +180,45 @@ __device__ void wg_build(WgLds& S, const WgScratch& X, const ModelDev& md,
         X.VX[j * n + i] = c_conj(x);
         X.VY[i * n + j] = y;
         X.VY[j * n + i] = c_conj(y);
+    }
+    __syncthreads();
+}
+
+// Hall tensor: v_z (from the third set of pencil partials) into VZ and, when spin is
+// given, the spin current Js_x = (s v_x + v_x s)/2 into JS (n x n each, Hermitian,
+// upper triangles summed and mirrored).
+__device__ void wg_build_tensor(WgLds& S, const ModelDev& md, const double2* __restrict__ T0,
+                                const double2* __restrict__ T2, const int* __restrict__ r0, int i0,
+                                const double* __restrict__ spin, double2* __restrict__ VZ,
+                                double2* __restrict__ JS) {
+    const int n = md.n;
+    const long long nn = (long long)n * n;
+    if (threadIdx.x < md.nR0) S.ph[threadIdx.x] = unit_phase((long long)i0 * r0[threadIdx.x], md.N0);
+    __syncthreads();
+    const int nu = n * (n + 1) / 2;
+    for (int e = threadIdx.x; e < nu; e += kWgThreads) {
+        const float b = 2.0f * n + 1.0f;
+        int i = (int)(0.5f * (b - sqrtf(b * b - 8.0f * (float)e)));
+        if (i * n - (i * (i - 1)) / 2 > e) --i;
+        else if ((i + 1) * n - ((i + 1) * i) / 2 <= e) ++i;
+        const int j = i + (e - (i * n - (i * (i - 1)) / 2));
+        const long long off = (long long)i * n + j;
+        double2 z = c_make(0.0, 0.0), x = z;
+        for (int rho = 0; rho < md.nR0; ++rho) {
+            z = c_fma(T2[(long long)rho * nn + off], S.ph[rho], z);
+            if (spin) x = c_add(x, c_scale((double)r0[rho], c_i(c_mul(T0[(long long)rho * nn + off], S.ph[rho]))));
+        }
+        if (i == j) {
+            z.y = 0.0;
+            x.y = 0.0;
+        }
+        VZ[i * n + j] = z;
+        VZ[j * n + i] = c_conj(z);
+        if (spin) {
+            x = c_scale(0.5 * (spin[i] + spin[j]), x);
+            JS[i * n + j] = x;
+            JS[j * n + i] = c_conj(x);
+        }
     }
     __syncthreads();
 }
@@ -923,14 +964,20 @@ __device__ bool wg_eigen_velocities(WgLds& S, const WgScratch& X, const ModelDev
 // ---------------------------------------------------------------------------
 // k_forward_wg
 // ---------------------------------------------------------------------------
-// SMALL (n <= 64): LDS-resident reduction, register back-transformation, matrix-core GEMMs
-template <bool SMALL>
+// SMALL (n <= 64): LDS-resident reduction, register back-transformation, matrix-core GEMMs.
+// TENSOR: also C = U^+ v_z U (in the pivot region, dead after the eigenvectors) and
+// D = U^+ Js_x U (in the K region, unused by the forward), four curvatures per band and
+// four Fermi sums per level, [slot][4][nF].
+template <bool SMALL, bool TENSOR>
 __global__ __launch_bounds__(kWgThreads, SMALL ? 2 : 1) void k_forward_wg(WgLaunch a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     WgLds& S = *reinterpret_cast<WgLds*>(smem_raw);
     const double eta2 = a.eta * a.eta;
+    constexpr int NC = TENSOR ? 4 : 1;
     const WgScratch X = wg_scratch(reinterpret_cast<double2*>(a.scratch), a.slot_elems, blockIdx.x);
     const double2* tbuf = reinterpret_cast<const double2*>(a.tbuf);
+    double2* VZ = reinterpret_cast<double2*>(X.DPM);
+    double2* JS = reinterpret_cast<double2*>(X.K);
     for (ItemSchedule sc = xcd_schedule(a.item_count); sc.next < sc.end; sc.next += sc.step) {
         const int item = sc.next;
         const BlockItem it = a.tb.blocks[a.item_begin + item];
@@ -939,13 +986,31 @@ __global__ __launch_bounds__(kWgThreads, SMALL ? 2 : 1) void k_forward_wg(WgLaun
         const long long nn = (long long)n * n;
         const double2* T0 = tbuf + it.tbuf_off;
         const double2* T1 = T0 + (long long)md.nR0 * nn;
+        const double2* T2 = T1 + (long long)md.nR0 * nn;
         const int* r0 = a.tb.r0val + md.r0_first;
         const double* ef = a.e_fermi + md.f_off;
-        double* part = a.partial + (long long)it.slot * a.nF;
+        const double* spin = (TENSOR && a.spin) ? a.spin + md.orb_off : nullptr;
+        double* part = a.partial + (long long)it.slot * a.nF * NC;
         for (int kk = 0; kk < it.count; ++kk) {
             const bool ok = wg_eigen_velocities<SMALL>(S, X, md, T0, T1, r0, it.i0 + kk, a.max_iter);
             if (!ok) atomicOr(a.status, kStatNoConv);
-            for (int i = threadIdx.x; i < n; i += kWgThreads) {
+            if constexpr (TENSOR) {
+                wg_build_tensor(S, md, T0, T2, r0, it.i0 + kk, spin, VZ, JS);
+                const double2* U = X.U;
+                double2* W = X.W;
+                wg_gemm<SMALL>(S, W, n, [=](int i, int k) { return VZ[i * n + k]; },
+                        [=](int k, int j) { return U[k * n + j]; });
+                wg_gemm<SMALL>(S, VZ, n, [=](int i, int k) { return c_conj(U[k * n + i]); },
+                        [=](int k, int j) { return W[k * n + j]; });
+                if (spin) {
+                    wg_gemm<SMALL>(S, W, n, [=](int i, int k) { return JS[i * n + k]; },
+                            [=](int k, int j) { return U[k * n + j]; });
+                    wg_gemm<SMALL>(S, JS, n, [=](int i, int k) { return c_conj(U[k * n + i]); },
+                            [=](int k, int j) { return W[k * n + j]; });
+                }
+            }
+            // Omega_i = -2 sum_{m != i} Im(P_im Q_mi) g(E_i - E_m) per operator pair
+            auto curv = [&](const double2* P, const double2* Q, int i) {
                 double om = 0.0;
                 const double ei = S.E[i];
                 for (int m = 0; m < n; ++m) {
@@ -953,18 +1018,39 @@ __global__ __launch_bounds__(kWgThreads, SMALL ? 2 : 1) void k_forward_wg(WgLaun
                     const double de = ei - S.E[m];
                     const double den = de * de + eta2;
                     if (den == 0.0) continue;
-                    const double2 x = X.VX[i * n + m], y = X.VY[m * n + i];
+                    const double2 x = P[i * n + m], y = Q[m * n + i];
                     om += (x.x * y.y + x.y * y.x) / den;
                 }
-                S.Om[i] = -2.0 * om;
+                return -2.0 * om;
+            };
+            for (int i = threadIdx.x; i < n; i += kWgThreads) {
+                S.Om[i] = curv(X.VX, X.VY, i);
+                if constexpr (TENSOR) {
+                    S.Om2[0][i] = curv(X.VY, VZ, i);
+                    S.Om2[1][i] = curv(VZ, X.VX, i);
+                    S.Om2[2][i] = spin ? curv(JS, X.VY, i) : 0.0;
+                }
             }
             __syncthreads();
             for (int j = threadIdx.x; j < a.nF; j += kWgThreads) {
                 const double efj = ef[j];
-                double s = 0.0;
-                for (int b = 0; b < n; ++b) s += occupation(S.E[b], efj, a.kT) * S.Om[b];
-                if (!isfinite(s)) atomicOr(a.status, kStatNonFinite);
-                part[j] = (kk == 0) ? s : part[j] + s;
+                double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+                for (int b = 0; b < n; ++b) {
+                    const double f = occupation(S.E[b], efj, a.kT);
+                    s0 += f * S.Om[b];
+                    if constexpr (TENSOR) {
+                        s1 += f * S.Om2[0][b];
+                        s2 += f * S.Om2[1][b];
+                        s3 += f * S.Om2[2][b];
+                    }
+                }
+                if (!isfinite(s0 + s1 + s2 + s3)) atomicOr(a.status, kStatNonFinite);
+                part[j] = (kk == 0) ? s0 : part[j] + s0;
+                if constexpr (TENSOR) {
+                    part[a.nF + j] = (kk == 0) ? s1 : part[a.nF + j] + s1;
+                    part[2 * a.nF + j] = (kk == 0) ? s2 : part[2 * a.nF + j] + s2;
+                    part[3 * a.nF + j] = (kk == 0) ? s3 : part[3 * a.nF + j] + s3;
+                }
             }
             __syncthreads();
         }
@@ -1117,8 +1203,10 @@ __global__ __launch_bounds__(kWgThreads, SMALL ? 2 : 1) void k_adjoint_wg(WgLaun
 static bool g_wg_attr = false;
 static hipError_t wg_attrs() {
     if (g_wg_attr) return hipSuccess;
-    const void* fns[] = {reinterpret_cast<const void*>(&k_forward_wg<true>),
-                         reinterpret_cast<const void*>(&k_forward_wg<false>),
+    const void* fns[] = {reinterpret_cast<const void*>(&k_forward_wg<true, false>),
+                         reinterpret_cast<const void*>(&k_forward_wg<false, false>),
+                         reinterpret_cast<const void*>(&k_forward_wg<true, true>),
+                         reinterpret_cast<const void*>(&k_forward_wg<false, true>),
                          reinterpret_cast<const void*>(&k_adjoint_wg<true>),
                          reinterpret_cast<const void*>(&k_adjoint_wg<false>)};
     for (const void* f : fns) {
@@ -1136,10 +1224,17 @@ hipError_t launch_forward_wg(const WgLaunch& L, int np, hipStream_t s) {
     hipError_t e = wg_attrs();
     if (e != hipSuccess) return e;
     const int grid = L.item_count < L.max_groups ? L.item_count : L.max_groups;
-    if (np <= 64)
-        hipLaunchKernelGGL(k_forward_wg<true>, dim3(grid), dim3(kWgThreads), kWgSmallLds, s, L);
-    else
-        hipLaunchKernelGGL(k_forward_wg<false>, dim3(grid), dim3(kWgThreads), sizeof(WgLds), s, L);
+    if (np <= 64) {
+        if (L.tensor)
+            hipLaunchKernelGGL((k_forward_wg<true, true>), dim3(grid), dim3(kWgThreads), kWgSmallLds, s, L);
+        else
+            hipLaunchKernelGGL((k_forward_wg<true, false>), dim3(grid), dim3(kWgThreads), kWgSmallLds, s, L);
+    } else {
+        if (L.tensor)
+            hipLaunchKernelGGL((k_forward_wg<false, true>), dim3(grid), dim3(kWgThreads), sizeof(WgLds), s, L);
+        else
+            hipLaunchKernelGGL((k_forward_wg<false, false>), dim3(grid), dim3(kWgThreads), sizeof(WgLds), s, L);
+    }
     return hipGetLastError();
 }
 

@@ -35,10 +35,13 @@ KUBO_E_NONFINITE = 6
 KUBO_F_GRAPH = 0x1
 KUBO_F_TIMING = 0x2
 KUBO_F_FORWARD_ONLY = 0x4
+KUBO_F_TENSOR = 0x8
+TENSOR_COMPONENTS = ("xy", "yz", "zx", "spin_xy")
 KUBO_F_DEBUG_SWEEPCAP = 0x100
 
 EXPORTED = ("kubo_plan", "kubo_ahc", "kubo_ahc_backward", "kubo_plan_device_status",
-            "kubo_plan_destroy", "kubo_status_string", "kubo_plan_info", "kubo_plan_kernel_time")
+            "kubo_plan_destroy", "kubo_status_string", "kubo_plan_info", "kubo_plan_kernel_time",
+            "kubo_ahc_tensor")
 
 
 class KuboError(RuntimeError):
@@ -77,6 +80,9 @@ def lib() -> ctypes.CDLL:
         L.kubo_ahc.restype = ctypes.c_int
         L.kubo_ahc.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_double, vp, vp,
                                ctypes.c_size_t, vp]
+        L.kubo_ahc_tensor.restype = ctypes.c_int
+        L.kubo_ahc_tensor.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_double, vp, vp, vp,
+                                      ctypes.c_size_t, vp]
         L.kubo_ahc_backward.restype = ctypes.c_int
         L.kubo_ahc_backward.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_double, vp, vp, vp,
                                         ctypes.c_size_t, vp]
@@ -126,6 +132,12 @@ def kubo_ahc(plan, t_ptr: int, ef_ptr: int, eta: float, kT: float, sigma_ptr: in
              ws_bytes: int, stream: int) -> int:
     return lib().kubo_ahc(plan, t_ptr, ef_ptr, float(eta), float(kT), sigma_ptr, ws_ptr,
                           int(ws_bytes), stream)
+
+
+def kubo_ahc_tensor(plan, t_ptr: int, ef_ptr: int, eta: float, kT: float, spin_ptr: int,
+                    sigma_ptr: int, ws_ptr: int, ws_bytes: int, stream: int) -> int:
+    return lib().kubo_ahc_tensor(plan, t_ptr, ef_ptr, float(eta), float(kT), spin_ptr, sigma_ptr,
+                                 ws_ptr, int(ws_bytes), stream)
 
 
 def kubo_ahc_backward(plan, t_ptr: int, ef_ptr: int, eta: float, kT: float, sbar_ptr: int,
@@ -276,6 +288,32 @@ class Plan:
             raise KuboError(st, "kubo_ahc")
         return out
 
+    def tensor(self, t, e_fermi, eta: float, kT: float, spin=None, out=None):
+        """[n_models, 4, n_fermi] float64: sigma_xy, sigma_yz, sigma_zx and the spin Hall
+        conductivity (spin: float64 CUDA tensor with one s_z value per orbital of every
+        model, or None), enqueued on the current stream.  Needs a KUBO_F_TENSOR plan."""
+        import torch
+
+        self._check_t(t)
+        self._check_f(e_fermi, "e_fermi")
+        sp = 0
+        if spin is not None:
+            if spin.dtype != torch.float64 or not spin.is_cuda or not spin.is_contiguous():
+                raise ValueError("spin must be a contiguous float64 CUDA tensor")
+            if spin.numel() != sum(n for n, _ in self.sizes):
+                raise ValueError("spin needs one value per orbital of every model")
+            sp = spin.data_ptr()
+        if out is None:
+            out = torch.empty(self.n_models, 4, self.n_fermi, dtype=torch.float64,
+                              device=t.device)
+        ws = self.workspace()
+        stream = torch.cuda.current_stream(t.device).cuda_stream
+        st = kubo_ahc_tensor(self.handle, t.data_ptr(), e_fermi.data_ptr(), eta, kT, sp,
+                             out.data_ptr(), ws.data_ptr(), self.ws_bytes, stream)
+        if st != KUBO_OK:
+            raise KuboError(st, "kubo_ahc_tensor")
+        return out
+
     def backward(self, t, e_fermi, eta: float, kT: float, sigma_bar, out=None):
         """dL/dRe t + i dL/dIm t for L = sum sigma_bar * sigma (complex128, like t)."""
         import torch
@@ -295,7 +333,8 @@ class Plan:
         return out
 
     def kernel_time(self, which: int = 0, reset: bool = False):
-        """(total_ms, launches, k_points) recorded under KUBO_F_TIMING."""
+        """(total_ms, launches, k_points) recorded under KUBO_F_TIMING (which: 0 forward,
+        1 backward, 2 tensor)."""
         st, ms, nl, kp = kubo_plan_kernel_time(self.handle, which, reset)
         if st != KUBO_OK:
             raise KuboError(st, "kubo_plan_kernel_time")

@@ -143,3 +143,25 @@ def test_plan_info_counts_slabs():
     assert kubo.kubo_plan_info(h)[1:] == (50, 2)
     kubo.kubo_plan_destroy(h)
     kubo.kubo_plan_destroy(None)
+
+
+def test_tensor_plan_sizes_and_argument_checks():
+    """A KUBO_F_TENSOR plan needs room for a third set of partial Bloch sums and four
+    result components; kubo_ahc_tensor on a plan without the flag is rejected before any
+    device work."""
+    d, keep = _desc(n=4, grid=(4, 3, 2))
+    st, h, wsb = kubo.kubo_plan([d], 3, kubo.KUBO_F_FORWARD_ONLY)
+    st2, h2, wsb2 = kubo.kubo_plan([d], 3, kubo.KUBO_F_FORWARD_ONLY | kubo.KUBO_F_TENSOR)
+    assert st == kubo.KUBO_OK and st2 == kubo.KUBO_OK
+    try:
+        assert wsb2 > wsb
+        fake = 0x1000  # never dereferenced
+        assert kubo.kubo_ahc_tensor(h, fake, fake, 1e-3, 0.0, 0, fake, fake, wsb, None) == \
+            kubo.KUBO_E_INVALID
+        assert kubo.kubo_ahc_tensor(h2, fake, fake, -1.0, 0.0, 0, fake, fake, wsb2, None) == \
+            kubo.KUBO_E_INVALID
+        assert kubo.kubo_ahc_tensor(h2, fake, fake, 1e-3, 0.0, 0, fake, fake, wsb2 - 1, None) == \
+            kubo.KUBO_E_WORKSPACE
+    finally:
+        kubo.kubo_plan_destroy(h)
+        kubo.kubo_plan_destroy(h2)
