@@ -32,6 +32,15 @@ def workload_fermi(cfg: int, wl=None):
     return np.array(out)
 
 
+# worst error/bound ratio of every parity comparison of the session; conftest
+# writes them to gpurun_out/parity_margins.json at the end of a GPU session
+MARGINS = []
+
+
+def record_margin(kind: str, what: str, ratio: float, rel: float):
+    MARGINS.append({"kind": kind, "case": what, "err_over_bound": float(ratio), "rel": rel})
+
+
 def assert_sigma_parity(got, ref, sabs, rel=1e-10, what=""):
     """|got - ref| <= rel * max(|ref|, S_abs) element by element.
 
@@ -41,7 +50,12 @@ def assert_sigma_parity(got, ref, sabs, rel=1e-10, what=""):
     ref = np.asarray(ref, float).reshape(-1)
     sabs = np.asarray(sabs, float).reshape(-1)
     bound = rel * np.maximum(np.abs(ref), sabs)
-    bad = np.nonzero(np.abs(got - ref) > bound)[0]
+    err = np.abs(got - ref)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ratio = np.where(bound > 0, err / bound, np.where(err > 0, np.inf, 0.0))
+    record_margin("sigma", what, ratio.max() if ratio.size else 0.0, rel)
+    print(f"parity {what}: max err/bound {ratio.max():.3e} (rel {rel:g})", flush=True)
+    bad = np.nonzero(err > bound)[0]
     if bad.size:
         i = bad[0]
         raise AssertionError(f"{what}: {bad.size} of {got.size} outside {rel:g}; first j={i}: "
@@ -53,3 +67,18 @@ def slab_sample(nk: int, count: int, seed: int):
     u = synth.uniform01(seed, 1)[0]
     kb = int(u * (nk - count))
     return kb, count
+
+
+def assert_grad_close(got, ref, rel, what=""):
+    """|G - G_ref| <= rel * max(|G_ref|, 1e-3 max|G_ref|) entry by entry."""
+    got = np.asarray(got).reshape(-1)
+    ref = np.asarray(ref).reshape(-1)
+    scale = np.abs(ref).max()
+    err = np.abs(got - ref)
+    bound = rel * np.maximum(np.abs(ref), 1e-3 * scale)
+    ratio = (err / bound).max() if bound.size and scale > 0 else (0.0 if err.max() == 0 else np.inf)
+    record_margin("gradient", what, ratio, rel)
+    print(f"gradient {what}: max err/bound {ratio:.3e} (rel {rel:g})", flush=True)
+    bad = np.nonzero(err > bound)[0]
+    assert bad.size == 0, (f"{what}: {bad.size} of {err.size} entries off; worst err/bound "
+                           f"{ratio:.3e}")

@@ -18,3 +18,19 @@ def oracle():
 
     O.build()
     return O
+
+
+def pytest_sessionfinish(session, exitstatus):
+    """Write the worst error/bound ratio of every parity comparison that ran."""
+    import json
+
+    try:
+        from _util import MARGINS
+    except ImportError:
+        return
+    if not MARGINS:
+        return
+    out = os.path.join(ROOT, "gpurun_out")
+    os.makedirs(out, exist_ok=True)
+    with open(os.path.join(out, "parity_margins.json"), "w") as f:
+        json.dump(MARGINS, f, indent=1)

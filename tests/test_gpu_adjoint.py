@@ -6,7 +6,7 @@ import pytest
 
 from paper_2309_06675_amd import kubo, synth
 
-from _util import workload_fermi
+from _util import assert_grad_close, record_margin, workload_fermi
 
 pytestmark = pytest.mark.gpu
 
@@ -28,15 +28,6 @@ def gpu_grad(torch, models, grid, ef, eta, kT, sbar, slabs=None, flags=0):
     st = plan.device_status()
     assert st == kubo.KUBO_OK, kubo.kubo_status_string(st)
     return g.cpu().numpy(), plan, t, efd, sb
-
-
-def assert_grad_close(got, ref, rel, what=""):
-    scale = np.abs(ref).max()
-    err = np.abs(got - ref)
-    bound = rel * np.maximum(np.abs(ref), 1e-3 * scale)
-    bad = np.nonzero(err > bound)[0]
-    assert bad.size == 0, (f"{what}: {bad.size} of {err.size} entries off; worst rel "
-                           f"{(err / np.maximum(np.abs(ref), 1e-3 * scale)).max():.3e}")
 
 
 @pytest.mark.parametrize("n,L,grid,kT,eta", [(3, 1, (3, 3, 2), 0.05, 0.05),
@@ -64,6 +55,22 @@ def test_gradient_through_exact_degeneracy(torch, oracle):
     ref = oracle.ahc_grad(m.t, m.R, (3, 3, 2), ef, 0.05, 0.05, sbar).reshape(-1)
     assert np.all(np.isfinite(got))
     assert_grad_close(got, ref, 1e-8, "doubled")
+
+
+@pytest.mark.parametrize("n,grid", [(20, (3, 2, 1)), (48, (2, 1, 1))])
+def test_gradient_through_exact_degeneracy_workgroup_class(torch, oracle, n, grid):
+    """t (x) I_2 at n = 40 and n = 96 (the workgroup adjoint kernel, both size classes):
+    every eigenvalue pair is closer than the kernel's threshold, so the eigenvector term
+    of every such pair takes the divided-difference limit."""
+    m = synth.doubled(synth.random_model(n, 1, 1.0, 8080 + n))
+    lo, hi = oracle.band_range(m.t, m.R, (2, 2, 1))
+    ef = np.linspace(lo + 0.2 * (hi - lo), hi - 0.2 * (hi - lo), 3)
+    sbar = np.array([1.0, -0.7, 0.2])
+    print(f"case grad doubled n={2 * n} grid={grid}", flush=True)
+    got, *_ = gpu_grad(torch, [m], grid, ef, 0.05, 0.05, sbar)
+    ref = oracle.ahc_grad(m.t, m.R, grid, ef, 0.05, 0.05, sbar).reshape(-1)
+    assert np.all(np.isfinite(got))
+    assert_grad_close(got, ref, 1e-8, f"doubled n={2 * n}")
 
 
 def test_gradient_slab_and_symmetry(torch, oracle):
@@ -185,6 +192,13 @@ def test_cfg3_finite_differences_50_entries(torch):
           % ((e1 / b1).max(), np.median(e1 / np.abs(a[:, 1])), (e2 / b2).max(),
              (e2 / np.maximum(np.abs(rr[:, 3]), floor)).max(), np.median(e2 / np.abs(rr[:, 3])),
              (a[:, 2] * h).max()), flush=True)
+    record_margin("fd_h1e-6", "cfg3 50 entries (bound with noise term)", (e1 / b1).max(), 1e-6)
+    record_margin("fd_h1e-6_plain", "cfg3 50 entries (plain 1e-6 bound, no noise term)",
+                  (e1 / (1e-6 * np.maximum(np.abs(a[:, 1]), floor))).max(), 1e-6)
+    record_margin("fd_richardson", "cfg3 first 20 entries (bound with noise term)",
+                  (e2 / b2).max(), 1e-6)
+    record_margin("fd_richardson_plain", "cfg3 first 20 entries (plain 1e-6 bound)",
+                  (e2 / (1e-6 * np.maximum(np.abs(rr[:, 3]), floor))).max(), 1e-6)
     assert np.all(e1 <= b1)
     assert np.all(e2 <= b2)
 

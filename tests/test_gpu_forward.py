@@ -104,6 +104,20 @@ def test_degenerate_spectrum_parity(torch, oracle, n):
     assert_sigma_parity(got[0], ref, sabs, what=f"doubled n={2 * n}")
 
 
+@pytest.mark.parametrize("n,grid", [(40, (3, 2, 2)), (64, (2, 1, 2))])
+def test_degenerate_spectrum_parity_workgroup_class(torch, oracle, n, grid):
+    """t (x) I_2 at n = 80 and n = 128: every eigenvalue doubly degenerate, so the
+    workgroup kernel for n > 64 takes its clustered-spectrum path (implicit QL with
+    accumulated rotations, then the back-transformation)."""
+    m = synth.doubled(synth.random_model(n, 1, 1.0, 6400 + n))
+    lo, hi = oracle.band_range(m.t, m.R, (2, 2, 1))
+    ef = np.linspace(lo, hi, 5)
+    print(f"case doubled n={2 * n} grid={grid}", flush=True)
+    got, _ = run_gpu(torch, [m], grid, ef, 1e-2, 0.02)
+    ref, sabs = oracle.ahc(m.t, m.R, grid, ef, 1e-2, 0.02, with_sabs=True)
+    assert_sigma_parity(got[0], ref, sabs, what=f"doubled n={2 * n}")
+
+
 @pytest.mark.parametrize("n", [12, 28])
 def test_graded_spectrum_parity(torch, oracle, n):
     """Orbitals scaled over four decades (D t D): many eigenvalues far below the spectral

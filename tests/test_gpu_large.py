@@ -6,7 +6,7 @@ import pytest
 
 from paper_2309_06675_amd import kubo, synth
 
-from _util import assert_sigma_parity, slab_sample, workload_fermi
+from _util import assert_grad_close, assert_sigma_parity, slab_sample, workload_fermi
 
 pytestmark = pytest.mark.gpu
 
@@ -51,6 +51,4 @@ def test_cfg4_sampled_slab_gradient(torch, oracle, cfg4):
     assert plan.device_status() == kubo.KUBO_OK
     ref = oracle.ahc_grad(m.t, m.R, wl.grid, ef, wl.eta_adjoint, wl.kT, sbar, k_begin=kb,
                           k_count=kc).reshape(-1)
-    scale = np.abs(ref).max()
-    err = np.abs(g - ref) / np.maximum(np.abs(ref), 1e-3 * scale)
-    assert err.max() <= 1e-8, err.max()
+    assert_grad_close(g, ref, 1e-8, "cfg4 slab")
