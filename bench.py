@@ -28,15 +28,42 @@ sys.path.insert(0, ROOT)
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 FP64 flop/clk
 
 
-def nominal_flops_per_k(n: int, n_R: int, n_f: int, fermi_dirac: bool) -> float:
-    """Algorithmic FP64 flops per k-point of the forward path.
+def bloch_flops_per_k(n: int, n_R: int, nR0: int, N0: int) -> float:
+    """FP64 flops per k-point of the Bloch sums of H, v_x, v_y as the kernels execute them
+    (sum-factorised over kx pencils).  Per pencil of N0 k-points: T_rho and Ty_rho, one
+    complex multiply-add each per lattice vector and matrix element (16 n_R n^2); per
+    k-point: the nR0-term rho-sums of H, v_x and v_y over the upper triangles
+    (3 x 8 x nR0 x n(n+1)/2)."""
+    return 16.0 * n_R * n * n / N0 + 12.0 * nR0 * n * (n + 1)
 
-    Direct Bloch sum of H, v_x, v_y over the upper triangles (12 n_R n(n+1)),
-    a Hermitian eigensolve counted as Householder + QR with vectors (24 n^3),
-    two rotations U^+ v U (32 n^3), the band-pair curvature (5 n^2) and the
-    Fermi sums (24 n N_F with Fermi-Dirac, 2 n N_F with a step)."""
-    return 12.0 * n_R * n * (n + 1) + 24.0 * n**3 + 32.0 * n**3 + 5.0 * n * n + \
+
+def direct_bloch_flops_per_k(n: int, n_R: int) -> float:
+    """The same sums taken directly over all lattice vectors (upper triangles): 12 n_R n(n+1)."""
+    return 12.0 * n_R * n * (n + 1)
+
+
+def forward_flops_per_k(n: int, n_R: int, nR0: int, N0: int, n_f: int, fermi_dirac: bool,
+                        direct: bool = False) -> float:
+    """Algorithmic FP64 flops per k-point of the forward path: the Bloch sums (sum-factorised
+    as executed, or direct), a Hermitian eigensolve counted as Householder + QR with vectors
+    (24 n^3), two rotations U^+ v U (32 n^3), the band-pair curvature (5 n^2) and the Fermi
+    sums (24 n N_F with Fermi-Dirac, 2 n N_F with a step)."""
+    s2 = direct_bloch_flops_per_k(n, n_R) if direct else bloch_flops_per_k(n, n_R, nR0, N0)
+    return s2 + 24.0 * n**3 + 32.0 * n**3 + 5.0 * n * n + \
         (24.0 if fermi_dirac else 2.0) * n * n_f
+
+
+def adjoint_flops_per_k(n: int, n_R: int, nR0: int, N0: int, n_f: int, k_block: int) -> float:
+    """Algorithmic FP64 flops per k-point of the backward pass: the forward recomputed, the
+    cotangents ((20 + 24 N_F) n), back through the eigendecomposition and the rotations
+    (ten complex products, 80 n^3), the per-k pencil sums of Hbar, vbar_x, vbar_y (3 x 8 x
+    nR0 x n^2) and the transposed Bloch sum per k-block of k_block points (16 n_R n^2)."""
+    return forward_flops_per_k(n, n_R, nR0, N0, n_f, True) + (20.0 + 24.0 * n_f) * n + \
+        80.0 * n**3 + 24.0 * nR0 * n * n + 16.0 * n_R * n * n / k_block
+
+
+def n_rx(model) -> int:
+    return len(set(int(x) for x in model.R[:, 0]))
 
 
 def fermi_levels(cfg: int, wl):
@@ -62,7 +89,8 @@ def measure_batched(steps: int, warmup: int):
     t_all = kubo.to_device_t(wl.models, dev)
     efd = torch.from_numpy(ef).to(dev)
     total_k = len(wl.models) * wl.n_k
-    flops = sum(nominal_flops_per_k(m.n, m.n_R, wl.n_fermi, wl.kT > 0) for m in wl.models) * wl.n_k
+    flops = sum(forward_flops_per_k(m.n, m.n_R, n_rx(m), wl.grid[0], wl.n_fermi, wl.kT > 0)
+                for m in wl.models) * wl.n_k
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     out = {}
@@ -113,20 +141,134 @@ def measure_batched(steps: int, warmup: int):
     out["models"] = len(wl.models)
     out["k_points_per_step"] = total_k
     out["batched_graph"] = {"ms_per_step": ms_b, "k_points_per_s": total_k / (ms_b / 1e3),
-                            "tflops_nominal": flops / (ms_b / 1e3) / 1e12,
+                            "tflops": flops / (ms_b / 1e3) / 1e12,
                             "frac": flops / (ms_b / 1e3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS}
     out["plain_per_model"] = {"ms_per_step": ms_p, "k_points_per_s": total_k / (ms_p / 1e3),
-                              "tflops_nominal": flops / (ms_p / 1e3) / 1e12,
+                              "tflops": flops / (ms_p / 1e3) / 1e12,
                               "frac": flops / (ms_p / 1e3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS}
     out["batched_over_plain"] = ms_p / ms_b
     out["max_abs_diff_batched_vs_plain"] = float(np.abs(sig_b - sig_p).max())
     return out
 
 
+def _timed_median(fn, reps: int, stream):
+    """Median over `reps` calls of fn() of the HIP-event time on `stream` (ms)."""
+    import torch
+
+    out = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        out.append(a.elapsed_time(b))
+    return float(np.median(out)), out
+
+
+def measure_adjoint_cfg3(reps: int = 5):
+    """The adjoint workload at its own shape: the n_orb = 32 model on its 64^3 grid, 16 Fermi
+    levels, eta = 1e-2, kT = 0.01; gradient of sum_j sigma_j w.r.t. all 343 x 32 x 32
+    hoppings.  Forward and backward each timed as the median of `reps` passes."""
+    import torch
+
+    from paper_2309_06675_amd import kubo, synth
+
+    wl = synth.workload(3)
+    m = wl.models[0]
+    ef = fermi_levels(3, wl)
+    dev = "cuda:0"
+    stream = torch.cuda.current_stream(dev)
+    plan = kubo.Plan([m], grid=wl.grid, n_fermi=wl.n_fermi, flags=kubo.KUBO_F_TIMING,
+                     device=dev)
+    t = kubo.to_device_t([m], dev)
+    efd = torch.from_numpy(ef).to(dev)
+    sig = torch.empty(1, wl.n_fermi, dtype=torch.float64, device=dev)
+    sbar = torch.ones(1, wl.n_fermi, dtype=torch.float64, device=dev)
+    grad = torch.empty_like(t)
+    plan.forward(t, efd, wl.eta_adjoint, wl.kT, out=sig)
+    plan.backward(t, efd, wl.eta_adjoint, wl.kT, sbar, out=grad)
+    torch.cuda.synchronize()
+    plan.kernel_time(0, reset=True)
+    plan.kernel_time(1, reset=True)
+    fms, fall = _timed_median(lambda: plan.forward(t, efd, wl.eta_adjoint, wl.kT, out=sig), reps,
+                              stream)
+    bms, ball = _timed_median(lambda: plan.backward(t, efd, wl.eta_adjoint, wl.kT, sbar,
+                                                    out=grad), reps, stream)
+    st = plan.device_status()
+    if st != kubo.KUBO_OK:
+        raise SystemExit(f"adjoint workload device status: {kubo.kubo_status_string(st)}")
+    kb = int(np.ceil(wl.grid[0] / np.ceil(wl.grid[0] / 32)))
+    ffk = forward_flops_per_k(m.n, m.n_R, n_rx(m), wl.grid[0], wl.n_fermi, True)
+    bfk = adjoint_flops_per_k(m.n, m.n_R, n_rx(m), wl.grid[0], wl.n_fermi, kb)
+    bk_ms, _, bk_k = plan.kernel_time(1)
+    return {"workload": wl.name, "k_points": wl.n_k, "reps": reps,
+            "forward_ms_median": fms, "backward_ms_median": bms,
+            "forward_ms_all": fall, "backward_ms_all": ball,
+            "forward_k_points_per_s": wl.n_k / (fms / 1e3),
+            "backward_k_points_per_s": wl.n_k / (bms / 1e3),
+            "adjoint_forward_ratio": bms / fms,
+            "backward_kernel_ms_per_pass": bk_ms / reps,
+            "flops_per_k": {"forward": ffk, "backward": bfk},
+            "frac": {"forward": ffk * wl.n_k / (fms / 1e3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
+                     "backward": bfk * wl.n_k / (bms / 1e3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS},
+            "grad_checksum": float(grad.abs().sum().item())}
+
+
+def measure_cfg4_slab(planes: int = 2, reps: int = 2):
+    """The n_orb = 128 workload (729 R, 128^3 grid, 256 Fermi levels; eta = 1e-3 forward,
+    1e-2 adjoint) on a slab of `planes` consecutive k_z planes from the middle of the grid
+    (planes x 128^2 k-points); median of `reps` passes each way."""
+    import torch
+
+    from paper_2309_06675_amd import kubo, synth
+
+    wl = synth.workload(4)
+    m = wl.models[0]
+    ef = fermi_levels(4, wl)
+    dev = "cuda:0"
+    stream = torch.cuda.current_stream(dev)
+    per_plane = wl.grid[0] * wl.grid[1]
+    kb = (wl.grid[2] // 2) * per_plane
+    kc = planes * per_plane
+    plan = kubo.Plan([m], grid=wl.grid, n_fermi=wl.n_fermi, slabs=[(kb, kc)], device=dev)
+    t = kubo.to_device_t([m], dev)
+    efd = torch.from_numpy(ef).to(dev)
+    sbar = torch.ones(1, wl.n_fermi, dtype=torch.float64, device=dev)
+    warm = kubo.Plan([m], grid=wl.grid, n_fermi=wl.n_fermi, slabs=[(kb, 2 * wl.grid[0])],
+                     device=dev)
+    warm.forward(t, efd, wl.eta, wl.kT)
+    warm.backward(t, efd, wl.eta_adjoint, wl.kT, sbar)
+    torch.cuda.synchronize()
+    del warm
+    print(f"cfg4 slab: {kc} k-points", file=sys.stderr, flush=True)
+    fms, fall = _timed_median(lambda: plan.forward(t, efd, wl.eta, wl.kT), reps, stream)
+    print(f"cfg4 slab forward {fms:.1f} ms", file=sys.stderr, flush=True)
+    bms, ball = _timed_median(lambda: plan.backward(t, efd, wl.eta_adjoint, wl.kT, sbar), reps,
+                              stream)
+    print(f"cfg4 slab backward {bms:.1f} ms", file=sys.stderr, flush=True)
+    st = plan.device_status()
+    if st != kubo.KUBO_OK:
+        raise SystemExit(f"cfg4 slab device status: {kubo.kubo_status_string(st)}")
+    kbb = int(np.ceil(wl.grid[0] / np.ceil(wl.grid[0] / 32)))
+    ffk = forward_flops_per_k(m.n, m.n_R, n_rx(m), wl.grid[0], wl.n_fermi, True)
+    bfk = adjoint_flops_per_k(m.n, m.n_R, n_rx(m), wl.grid[0], wl.n_fermi, kbb)
+    return {"workload": wl.name, "slab": {"k_begin": kb, "k_count": kc,
+                                          "what": f"{planes} k_z planes from the middle"},
+            "reps": reps, "forward_ms_median": fms, "backward_ms_median": bms,
+            "forward_k_points_per_s": kc / (fms / 1e3),
+            "backward_k_points_per_s": kc / (bms / 1e3),
+            "adjoint_forward_ratio": bms / fms,
+            "flops_per_k": {"forward": ffk, "backward": bfk},
+            "frac": {"forward": ffk * kc / (fms / 1e3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
+                     "backward": bfk * kc / (bms / 1e3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS}}
+
+
 def measure_large(adjoint: bool = True, parts: int = 16):
-    """The n_orb = 128 workload (729 R, 128^3 grid, 256 Fermi levels): the forward at
-    eta = 1e-3 and the adjoint at eta = 1e-2 over the whole grid, enqueued as `parts`
-    consecutive k-slabs (slabs add up exactly; each slab prints a progress line)."""
+    """The n_orb = 128 workload over its whole 128^3 grid (forward at eta = 1e-3, adjoint at
+    eta = 1e-2), enqueued as `parts` consecutive k-slabs (slabs add up exactly; each slab
+    prints a progress line).  Not part of the default run (about three minutes)."""
     import torch
 
     from paper_2309_06675_amd import kubo, synth
@@ -141,45 +283,29 @@ def measure_large(adjoint: bool = True, parts: int = 16):
     cuts = [wl.n_k * i // parts for i in range(parts + 1)]
     plans = [kubo.Plan([m], grid=wl.grid, n_fermi=wl.n_fermi, device=dev,
                        slabs=[(cuts[i], cuts[i + 1] - cuts[i])]) for i in range(parts)]
-    warm = kubo.Plan([m], grid=wl.grid, n_fermi=wl.n_fermi, slabs=[(0, 4 * wl.grid[0])],
-                     device=dev)
-    warm.forward(t, efd, wl.eta, wl.kT)
-    warm.backward(t, efd, wl.eta_adjoint, wl.kT, torch.ones(1, wl.n_fermi, dtype=torch.float64,
-                                                            device=dev))
-    torch.cuda.synchronize()
-
-    def timed(fn):
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        r = fn()
-        b.record(stream)
-        torch.cuda.synchronize()
-        return r, a.elapsed_time(b)
-
+    sbar = torch.ones(1, wl.n_fermi, dtype=torch.float64, device=dev)
     sig = torch.zeros(1, wl.n_fermi, dtype=torch.float64, device=dev)
     fms = 0.0
     for i, p in enumerate(plans):
-        s_i, ms = timed(lambda: p.forward(t, efd, wl.eta, wl.kT))
+        ms, _ = _timed_median(lambda: sig.add_(p.forward(t, efd, wl.eta, wl.kT)), 1, stream)
         assert p.device_status() == kubo.KUBO_OK
-        sig += s_i
         fms += ms
         print(f"large forward slab {i + 1}/{parts}: {ms:.1f} ms", file=sys.stderr, flush=True)
-    fpk = nominal_flops_per_k(m.n, m.n_R, wl.n_fermi, True)
+    fpk = forward_flops_per_k(m.n, m.n_R, n_rx(m), wl.grid[0], wl.n_fermi, True)
     out = {"workload": wl.name, "k_points": wl.n_k, "forward_ms": fms,
            "forward_k_points_per_s": wl.n_k / (fms / 1e3),
-           "forward_frac_nominal": fpk * wl.n_k / (fms / 1e3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
+           "forward_frac": fpk * wl.n_k / (fms / 1e3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
            "sigma_sum": float(sig.sum().item())}
     if adjoint:
-        sbar = torch.ones(1, wl.n_fermi, dtype=torch.float64, device=dev)
         g = torch.zeros_like(t)
         bms = 0.0
         for i, p in enumerate(plans):
-            g_i, ms = timed(lambda: p.backward(t, efd, wl.eta_adjoint, wl.kT, sbar))
+            ms, _ = _timed_median(lambda: g.add_(p.backward(t, efd, wl.eta_adjoint, wl.kT,
+                                                            sbar)), 1, stream)
             assert p.device_status() == kubo.KUBO_OK
-            g += g_i
             bms += ms
-            print(f"large adjoint slab {i + 1}/{parts}: {ms:.1f} ms", file=sys.stderr, flush=True)
+            print(f"large adjoint slab {i + 1}/{parts}: {ms:.1f} ms", file=sys.stderr,
+                  flush=True)
         out.update({"adjoint_ms": bms, "adjoint_k_points_per_s": wl.n_k / (bms / 1e3),
                     "adjoint_forward_ratio": bms / fms,
                     "grad_abs_sum": float(g.abs().sum().item())})
@@ -197,17 +323,19 @@ def kernel_source_digest() -> str:
     return h.hexdigest()
 
 
-def recorded_traffic():
-    """HBM bytes per launch of the dominant kernel from the committed counter runs
-    (profiles/traffic_k_forward_wave_n32.json), or None if the kernel changed since."""
-    path = os.path.join(ROOT, "profiles", "traffic_k_forward_wave_n32.json")
+def recorded_counters():
+    """The committed counter record of the dominant kernel
+    (profiles/counters_k_forward_wave_n32.json: HBM bytes per launch from FETCH_SIZE and
+    WRITE_SIZE scaled by a plain copy, executed FP64 flops per launch, LDS bank conflicts),
+    or None if the kernel's sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "counters_k_forward_wave_n32.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
     if rec.get("source_sha256") != kernel_source_digest():
         return None
-    return rec.get("bytes_per_launch")
+    return rec
 
 
 def copy_calibration(mbytes: int):
@@ -224,19 +352,64 @@ def copy_calibration(mbytes: int):
     return 0
 
 
-def cpu_baseline(model, wl, ef, sample: int):
-    """The CPU oracle, untuned, on a contiguous slab of `sample` k-points."""
+def flop_calibration(mbytes: int):
+    """Elementwise FP64 kernels of known work (counter calibration): a + b (one add per
+    element) and a + b * c (one multiply-add per element) over mbytes of doubles each."""
+    import torch
+
+    n = mbytes * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.full_like(a, 0.5)
+    c = torch.full_like(a, 0.25)
+    torch.cuda.synchronize()
+    d = a + b
+    e = torch.addcmul(a, b, c)
+    torch.cuda.synchronize()
+    print(json.dumps({"elements": n, "add_flops": n, "fma_flops": 2 * n,
+                      "check": float(d[0] + e[0])}), flush=True)
+    return 0
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(model, wl, ef, sample: int, single_sample: int):
+    """The CPU oracle, untuned, on a contiguous slab of `sample` k-points from the middle of
+    the grid with all threads the process may use, and on `single_sample` k-points with one
+    thread.  Cost per k-point is the same everywhere on the grid, so k-points/s extrapolates
+    linearly to the full grid."""
     from oracle import oracle as O
 
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
     kb = (wl.n_k // 2) - sample // 2
     t0 = time.perf_counter()
     O.ahc(model.t, model.R, wl.grid, ef, wl.eta, wl.kT, k_begin=kb, k_count=sample,
           nthreads=threads)
     dt = time.perf_counter() - t0
-    return {"value": sample / dt, "unit": "k-points/s", "cores": threads, "kind": "oracle",
-            "sample": f"{sample} consecutive k-points (flat index {kb}..{kb + sample - 1}) of the "
-                      f"same model, grid and Fermi levels; {dt:.2f} s wall on {threads} threads"}
+    out = {"value": sample / dt, "unit": "k-points/s", "cores": threads, "kind": "oracle",
+           "sample": f"{sample} consecutive k-points (flat index {kb}..{kb + sample - 1}) of the "
+                     f"same model, grid and Fermi levels; {dt:.2f} s wall on {threads} threads; "
+                     f"extrapolated: the full {wl.n_k}-point grid would take "
+                     f"{wl.n_k / (sample / dt):.0f} s",
+           "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+           "affinity_cpus": len(os.sched_getaffinity(0))}
+    if single_sample > 0:
+        t0 = time.perf_counter()
+        O.ahc(model.t, model.R, wl.grid, ef, wl.eta, wl.kT, k_begin=kb, k_count=single_sample,
+              nthreads=1)
+        d1 = time.perf_counter() - t0
+        out["single_core"] = {"value": single_sample / d1, "unit": "k-points/s",
+                              "sample": f"{single_sample} k-points from flat index {kb}; "
+                                        f"{d1:.2f} s wall on 1 thread (extrapolated)"}
+    return out
 
 
 def main(argv=None):
@@ -244,33 +417,41 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--cpu-sample", type=int, default=4096,
-                    help="k-points the CPU oracle is timed on (0 skips it)")
+    ap.add_argument("--cpu-sample", type=int, default=20480,
+                    help="k-points the CPU oracle is timed on with all threads (0 skips it)")
+    ap.add_argument("--cpu-single-sample", type=int, default=1024,
+                    help="k-points the CPU oracle is timed on with one thread (0 skips it)")
     ap.add_argument("--k-block", type=int, default=0, help="override the k-block of the plan")
     ap.add_argument("--threads", type=int, default=0,
                     help="per-k kernel: 64 = one wavefront, 256 = one workgroup (0 = default)")
-    ap.add_argument("--adjoint-steps", type=int, default=1,
-                    help="timed backward passes for the adjoint/forward ratio (0 skips)")
+    ap.add_argument("--adjoint-reps", type=int, default=5,
+                    help="timed passes (median) of the adjoint workload, each way (0 skips)")
+    ap.add_argument("--large-reps", type=int, default=2,
+                    help="timed passes (median) of the n_orb = 128 slab, each way (0 skips)")
     ap.add_argument("--batched-steps", type=int, default=1,
                     help="timed steps of the 200-model batched workload (0 skips)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run one device copy of MB megabytes (counter calibration)")
+    ap.add_argument("--flop-calibration", type=int, default=0, metavar="MB",
+                    help="only run two elementwise FP64 kernels on MB megabytes (counter calibration)")
     ap.add_argument("--large", action="store_true",
-                    help="only run the n_orb = 128 workload (forward + adjoint) and print it")
+                    help="only run the n_orb = 128 workload over its full grid and print it")
+    ap.add_argument("--legs", default="forward,adjoint,n128,batched,cpu",
+                    help="comma-separated legs to run (forward is always run; for profiling)")
     args = ap.parse_args(argv)
-    if args.copy_calibration > 0:
-        return copy_calibration(args.copy_calibration)
-    if args.large:
-        if args.gpus != 1:
-            print("bench.py measures one GPU", file=sys.stderr)
-            return 2
-        print(json.dumps(measure_large()), flush=True)
-        return 0
+    legs = set(args.legs.split(","))
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(k-slabs shard across GPUs by design, but this build runs on one GPU only)",
               file=sys.stderr)
         return 2
+    if args.copy_calibration > 0:
+        return copy_calibration(args.copy_calibration)
+    if args.flop_calibration > 0:
+        return flop_calibration(args.flop_calibration)
+    if args.large:
+        print(json.dumps(measure_large()), flush=True)
+        return 0
 
     import torch
 
@@ -285,8 +466,8 @@ def main(argv=None):
     tiles = "auto"
     if args.k_block > 0 or args.threads > 0:
         tiles = [(model.n, args.threads, args.k_block if args.k_block > 0 else 32)]
-    plan = kubo.Plan([model], grid=wl.grid, n_fermi=wl.n_fermi, flags=kubo.KUBO_F_TIMING,
-                     tiles=tiles, device=dev)
+    plan = kubo.Plan([model], grid=wl.grid, n_fermi=wl.n_fermi,
+                     flags=kubo.KUBO_F_TIMING | kubo.KUBO_F_FORWARD_ONLY, tiles=tiles, device=dev)
     t = kubo.to_device_t([model], dev)
     efd = torch.from_numpy(ef).to(dev)
     sigma = torch.empty(1, wl.n_fermi, dtype=torch.float64, device=dev)
@@ -317,8 +498,26 @@ def main(argv=None):
     total_k = plan.total_k * args.steps
     value = total_k / (ms / 1e3)
 
-    fpk = nominal_flops_per_k(model.n, model.n_R, wl.n_fermi, wl.kT > 0)
-    achieved = fpk * kpts / (k_ms / 1e3) / 1e12
+    nr0 = n_rx(model)
+    fpk = forward_flops_per_k(model.n, model.n_R, nr0, wl.grid[0], wl.n_fermi, wl.kT > 0)
+    fpk_direct = forward_flops_per_k(model.n, model.n_R, nr0, wl.grid[0], wl.n_fermi,
+                                     wl.kT > 0, direct=True)
+    # the per-k kernel executes everything but the pencil sums (a separate kernel)
+    fpk_kernel = fpk - 16.0 * model.n_R * model.n**2 / wl.grid[0]
+    achieved = fpk_kernel * kpts / (k_ms / 1e3) / 1e12
+    rec = recorded_counters()
+    traffic = rec["bytes_per_launch"] if rec else None
+    per_launch_k = kpts / max(launches, 1)
+    counters = None
+    if rec:
+        # executed FP64 work from the counters (issued lanes, MFMA at 512 flops per MOP),
+        # over the live launch time of this run
+        exe = rec["fp64_flops_per_k_point"] * kpts / (k_ms / 1e3) / 1e12
+        counters = {"executed_fp64_tflops": exe, "executed_frac": exe / FP64_VECTOR_PEAK_TFLOPS,
+                    "executed_flops_per_k": rec["fp64_flops_per_k_point"],
+                    "lds_bank_conflicts_per_access": rec["lds_bank_conflicts_per_access"],
+                    "hbm_bytes_per_k": rec["bytes_per_launch"] / rec["k_points_per_launch_mean"],
+                    "source": "profiles/" + rec["summary"]}
     out = {
         "metric": "k-points/s for sigma_xy (n_orb=32, FP64) at 1 MI355X",
         "value": value,
@@ -337,35 +536,33 @@ def main(argv=None):
                    "eta": wl.eta, "kT": wl.kT, "model_seed": 1000, "parallelism": "single-gpu"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-                     "traffic": recorded_traffic(), "kernel": "k_forward_wave<32> (per-k fused)",
-                     "flops_per_k": fpk, "kernel_ms_per_step": k_ms / args.steps,
-                     "launches_per_step": launches / args.steps},
+                     "traffic": traffic, "traffic_unit": "HBM bytes per launch",
+                     "traffic_per_step": (traffic * launches / args.steps) if traffic else None,
+                     "kernel": "k_forward_wave<32> (per-k fused)",
+                     "flop_model": "sum-factorised Bloch sums as executed + 24n^3 eigensolve + "
+                                   "32n^3 rotations + 5n^2 curvature + 24 n N_F Fermi sums",
+                     "flops_per_k_kernel": fpk_kernel, "flops_per_k_step": fpk,
+                     "k_points_per_launch": per_launch_k,
+                     "kernel_ms_per_step": k_ms / args.steps,
+                     "launches_per_step": launches / args.steps,
+                     "direct_sum_model": {"flops_per_k": fpk_direct,
+                                          "tflops": fpk_direct * total_k / (ms / 1e3) / 1e12,
+                                          "note": "Bloch sums counted as the direct sum over "
+                                                  "all lattice vectors; not executed"},
+                     "counters": counters},
+        "step_tflops": fpk * total_k / (ms / 1e3) / 1e12,
         "sigma_checksum": float(sigma.sum().item()),
     }
-    if args.adjoint_steps > 0:
-        # adjoint of sum_j sbar_j sigma_j over the same grid (all hoppings), same stream
-        sbar = torch.ones(1, wl.n_fermi, dtype=torch.float64, device=dev)
-        grad = torch.empty_like(t)
-        plan.backward(t, efd, wl.eta, wl.kT, sbar, out=grad)
-        torch.cuda.synchronize()
-        plan.kernel_time(1, reset=True)
-        start.record(stream)
-        for _ in range(args.adjoint_steps):
-            plan.backward(t, efd, wl.eta, wl.kT, sbar, out=grad)
-        stop.record(stream)
-        torch.cuda.synchronize()
-        st = plan.device_status()
-        if st != kubo.KUBO_OK:
-            raise SystemExit(f"device status (backward): {kubo.kubo_status_string(st)}")
-        bms = start.elapsed_time(stop) / args.adjoint_steps
-        out["adjoint"] = {"ms_per_step": bms, "k_points_per_s": plan.total_k / (bms / 1e3),
-                          "adjoint_forward_ratio": bms / (ms / args.steps),
-                          "kernel_ms_per_step": plan.kernel_time(1)[0] / args.adjoint_steps,
-                          "grad_checksum": float(grad.abs().sum().item())}
-    if args.batched_steps > 0:
+    del plan
+    if args.adjoint_reps > 0 and "adjoint" in legs:
+        out["adjoint"] = measure_adjoint_cfg3(args.adjoint_reps)
+    if args.large_reps > 0 and "n128" in legs:
+        out["n128_slab"] = measure_cfg4_slab(reps=args.large_reps)
+    if args.batched_steps > 0 and "batched" in legs:
         out["batched"] = measure_batched(args.batched_steps, 1)
-    if args.cpu_sample > 0:
-        out["cpu_baseline"] = cpu_baseline(model, wl, ef[0], args.cpu_sample)
+    if args.cpu_sample > 0 and "cpu" in legs:
+        out["cpu_baseline"] = cpu_baseline(model, wl, ef[0], args.cpu_sample,
+                                           args.cpu_single_sample)
     print(json.dumps(out), flush=True)
     return 0
 
