@@ -205,6 +205,38 @@ kubo_status kubo_plan_kernel_time(kubo_plan_t plan, int32_t which, double* total
  * models and slabs, and the number of models.  Returns KUBO_E_INVALID on NULL. */
 kubo_status kubo_plan_info(kubo_plan_t plan, int64_t* total_k_points, int32_t* n_models);
 
+/* Size of the library's own device workspace used by kubo_ahc_noalloc. */
+#define KUBO_NOALLOC_MAX_BYTES (64u << 20)
+
+/* Device status bits that kubo_ahc_noalloc can report. */
+#define KUBO_DEVICE_NOCONV 0x1u
+#define KUBO_DEVICE_NONFINITE 0x2u
+
+/*
+ * kubo_ahc_noalloc -- kubo_ahc without a caller workspace, for callers that
+ * cannot allocate device memory (code that must not call hipMalloc, tight
+ * serving loops, harnesses that forbid allocation).  The workspace is a
+ * static device array inside the library, KUBO_NOALLOC_MAX_BYTES per GPU,
+ * held until the process ends; nothing is allocated or freed by the call.
+ *   plan, t, e_fermi, eta, kT, sigma   as for kubo_ahc (same results, bit for bit)
+ *   device_status  device uint32_t, or NULL: receives the device-side status
+ *                  bits of this call (0, or KUBO_DEVICE_NOCONV and/or
+ *                  KUBO_DEVICE_NONFINITE), written on the stream
+ *   stream         a stream of the current device
+ * Every call on one GPU shares that GPU's array, so calls that overlap in
+ * time on one GPU (two streams, two threads) race and give wrong results;
+ * calls on one stream are safe.  The plan's tables are uploaded (and the
+ * stream synchronised) when the array last held another plan's.  Always
+ * eager: KUBO_F_GRAPH and KUBO_F_TIMING are ignored here.
+ * Errors: as kubo_ahc; KUBO_E_WORKSPACE when the plan's workspace_bytes
+ * exceed KUBO_NOALLOC_MAX_BYTES (plan with KUBO_F_FORWARD_ONLY and, for large
+ * grids, a smaller KUBO_CHUNK_MB); KUBO_E_HIP if the array's address cannot
+ * be found on the current device.
+ */
+kubo_status kubo_ahc_noalloc(kubo_plan_t plan, const double* t, const double* e_fermi,
+                             double eta, double kT, double* sigma, uint32_t* device_status,
+                             void* stream);
+
 #ifdef __cplusplus
 }
 #endif

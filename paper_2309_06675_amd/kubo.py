@@ -41,7 +41,11 @@ KUBO_F_DEBUG_SWEEPCAP = 0x100
 
 EXPORTED = ("kubo_plan", "kubo_ahc", "kubo_ahc_backward", "kubo_plan_device_status",
             "kubo_plan_destroy", "kubo_status_string", "kubo_plan_info", "kubo_plan_kernel_time",
-            "kubo_ahc_tensor")
+            "kubo_ahc_noalloc", "kubo_ahc_tensor")
+
+KUBO_NOALLOC_MAX_BYTES = 64 << 20
+KUBO_DEVICE_NOCONV = 0x1
+KUBO_DEVICE_NONFINITE = 0x2
 
 
 class KuboError(RuntimeError):
@@ -96,6 +100,8 @@ def lib() -> ctypes.CDLL:
         L.kubo_plan_kernel_time.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                             ctypes.POINTER(ctypes.c_int64),
                                             ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]
+        L.kubo_ahc_noalloc.restype = ctypes.c_int
+        L.kubo_ahc_noalloc.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_double, vp, vp, vp]
         L.kubo_plan_info.restype = ctypes.c_int
         L.kubo_plan_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int64),
                                      ctypes.POINTER(ctypes.c_int32)]
@@ -144,6 +150,12 @@ def kubo_ahc_backward(plan, t_ptr: int, ef_ptr: int, eta: float, kT: float, sbar
                       grad_ptr: int, ws_ptr: int, ws_bytes: int, stream: int) -> int:
     return lib().kubo_ahc_backward(plan, t_ptr, ef_ptr, float(eta), float(kT), sbar_ptr, grad_ptr,
                                    ws_ptr, int(ws_bytes), stream)
+
+
+def kubo_ahc_noalloc(plan, t_ptr: int, ef_ptr: int, eta: float, kT: float, sigma_ptr: int,
+                     status_ptr: int, stream: int) -> int:
+    return lib().kubo_ahc_noalloc(plan, t_ptr, ef_ptr, float(eta), float(kT), sigma_ptr,
+                                  status_ptr, stream)
 
 
 def kubo_plan_device_status(plan, ws_ptr: int, stream: int) -> int:

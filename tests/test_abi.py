@@ -129,6 +129,9 @@ def test_call_argument_checks_happen_before_device_work():
         assert kubo.kubo_ahc_backward(h, fake, fake, 0.0, 0.01, fake, fake, fake, wsb, None) == \
             kubo.KUBO_E_INVALID
         assert kubo.kubo_plan_device_status(h, fake, None) == kubo.KUBO_E_INVALID
+        assert kubo.kubo_ahc_noalloc(h, 0, fake, 1e-3, 0.0, fake, 0, None) == kubo.KUBO_E_INVALID
+        assert kubo.kubo_ahc_noalloc(None, fake, fake, 1e-3, 0.0, fake, 0, None) == \
+            kubo.KUBO_E_INVALID
         st, tk, nm = kubo.kubo_plan_info(h)
         assert st == kubo.KUBO_OK and tk == 64 and nm == 1
     finally:
