@@ -8,9 +8,11 @@
 // matrices of the k-point being processed live in a per-workgroup slice of the
 // workspace (it stays in L2 / the last-level cache) instead of registers and
 // LDS, which cannot hold them all at n = 128.  Two instantiations: n <= 64
-// (reduction on an LDS copy, register back-transformation, products on the
-// FP64 matrix cores) and n <= 128 (reduction in the slice, LDS-staged
-// back-transformation, products through 32 x 32 LDS tiles).
+// (reduction on an LDS copy of the matrix, products on the FP64 matrix cores,
+// two workgroups per CU) and n <= 128 (reduction on the lower triangle packed
+// into LDS, products through 32 x 32 LDS tiles, one workgroup per CU with the
+// CU's whole LDS); both keep the twisted factorisations' pivots in LDS and U in
+// registers for the back-transformation.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -24,6 +26,10 @@
 namespace kubo {
 
 constexpr int kWgThreads = 256;
+// Eigenvalues closer than this fraction of the spectral span send the k-point to the
+// implicit-QL path; wider gaps take one twisted factorisation per eigenvector, whose
+// error (like that of any backward-stable eigensolver) is of order eps |T| / gap.
+constexpr double kWgClusterGap = 1e-5;
 constexpr int kWgMaxN = 128;
 constexpr int kTile = 32;
 
@@ -48,19 +54,31 @@ struct WgLds {
     double Om[kWgMaxN];
     double phi[kWgMaxN];
     double dphi[kWgMaxN];
-    double2 ta[kTile * (kTile + 1)];
-    double2 tb[kTile * (kTile + 1)];
     // Hall tensor: curvatures of the (v_y, v_z), (v_z, v_x), (Js_x, v_y) pairs
     double Om2[3][kWgMaxN];
+    // From here to the end of the dynamic allocation: one scratch region shared by
+    // phases that never overlap (GEMM tiles, staged reflectors, twisted pivots)
+    double2 ta[kTile * (kTile + 1)];
+    double2 tb[kTile * (kTile + 1)];
 };
 
 // The n <= 64 kernels get 80 KB of LDS per workgroup (two workgroups per CU):
 // the n x n matrix of the Householder reduction from S.lam on, and the four
 // wavefronts' partial sums of p (4 x 64 complex) at the very end.
 constexpr size_t kWgSmallLds = 80 * 1024;
+// The n <= 128 kernels (one workgroup per CU) take the whole LDS of the CU.
+constexpr size_t kWgBigLds = 160 * 1024;
 constexpr int kWgSmallN = 64;
 constexpr size_t kWgSmallPart = sizeof(double2) * (kWgThreads / 64) * kWgSmallN;
 static_assert(sizeof(WgLds) <= kWgSmallLds, "LDS layout");
+static_assert(offsetof(WgLds, ta) + sizeof(double2) * kWgMaxN * (kWgMaxN + 1) / 2 <= kWgBigLds,
+              "packed matrix in the LDS scratch region");
+// the scratch region: from ta to the end of the dynamic allocation
+__device__ __forceinline__ double* wg_region(WgLds& S) { return reinterpret_cast<double*>(S.ta); }
+template <bool SMALL>
+__host__ __device__ constexpr size_t wg_region_doubles() {
+    return ((SMALL ? kWgSmallLds : kWgBigLds) - offsetof(WgLds, ta)) / sizeof(double);
+}
 static_assert(offsetof(WgLds, lam) + sizeof(double2) * kWgSmallN * kWgSmallN <= kWgSmallLds - kWgSmallPart,
               "LDS matrix region");
 
@@ -224,16 +242,43 @@ __device__ void wg_build_tensor(WgLds& S, const ModelDev& md, const double2* __r
 }
 
 // ---------------------------------------------------------------------------
-// step 2a: Householder reduction of P to real tridiagonal (S.d, S.e)
+// step 2a for n <= 128 on the lower triangle of the matrix packed into LDS
+// (element (r, c), c <= r, at r (r + 1) / 2 + c; 132 KB at n = 128), the same
+// steps as wg_tridiag: column k through LDS, its reflector, p = A22 v (two
+// threads per row, the upper triangle read as the conjugate of the lower one),
+// w, and the rank-2 update of the trailing lower triangle (two threads per
+// column, lanes over columns so that a row's elements are consecutive).  The
+// reflectors are written back into P (column k below the diagonal) for the
+// back-transformation.
 // ---------------------------------------------------------------------------
-__device__ void wg_tridiag(WgLds& S, double2* __restrict__ P, int n) {
+__device__ __forceinline__ int tri_idx(int r, int c) { return (r * (r + 1)) / 2 + c; }
+
+__device__ void wg_tridiag_packed(WgLds& S, double2* __restrict__ P, int n, double2* __restrict__ L) {
     const int tid = threadIdx.x;
+    const int nt = n * (n + 1) / 2;
+    // row of packed element e: the largest r with r (r + 1) / 2 <= e (float estimate, corrected)
+    auto tri_row = [](int e) {
+        int r = (int)(0.5f * (sqrtf(8.0f * (float)e + 1.0f) - 1.0f));
+        if (tri_idx(r, 0) > e) --r;
+        else if (tri_idx(r + 1, 0) <= e) ++r;
+        return r;
+    };
+    for (int e = tid; e < nt; e += kWgThreads) {
+        const int r = tri_row(e);
+        L[e] = P[r * n + (e - tri_idx(r, 0))];
+    }
+    __syncthreads();
+    auto rcp = [](double x) {
+        const double r0 = __builtin_amdgcn_rcp(x);
+        return fma(r0, fma(-x, r0, 1.0), r0);
+    };
     for (int k = 0; k < n - 1; ++k) {
-        const int m = n - k - 1;
-        for (int r = k + 1 + tid; r < n; r += kWgThreads) S.xv[r] = P[r * n + k];
-        __syncthreads();
         double part = 0.0;
-        for (int r = k + 2 + tid; r < n; r += kWgThreads) part += S.xv[r].x * S.xv[r].x + S.xv[r].y * S.xv[r].y;
+        for (int r = k + 1 + tid; r < n; r += kWgThreads) {
+            const double2 x = L[tri_idx(r, k)];
+            S.xv[r] = x;
+            if (r > k + 1) part = fma(x.x, x.x, fma(x.y, x.y, part));
+        }
         const double xn2 = wg_sum(part, S.red);
         const double2 alpha = S.xv[k + 1];
         double beta;
@@ -245,27 +290,32 @@ __device__ void wg_tridiag(WgLds& S, double2* __restrict__ P, int n) {
         } else {
             const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn2);
             beta = -copysign(nrm, alpha.x);
-            tau = c_make((beta - alpha.x) / beta, -alpha.y / beta);
+            const double ib = rcp(beta);
+            tau = c_make((beta - alpha.x) * ib, -alpha.y * ib);
             const double ar = alpha.x - beta, ai = alpha.y;
-            const double den = 1.0 / (ar * ar + ai * ai);
+            const double den = rcp(ar * ar + ai * ai);
             scal = c_make(ar * den, -ai * den);
         }
         if (tid == 0) {
-            S.d[k] = P[k * n + k].x;
+            S.d[k] = L[tri_idx(k, k)].x;
             S.e[k] = beta;
             S.tau[k] = tau;
         }
         for (int r = k + 1 + tid; r < n; r += kWgThreads) {
             const double2 v = (r == k + 1) ? c_make(1.0, 0.0) : c_mul(S.xv[r], scal);
             S.vv[r] = v;
-            P[r * n + k] = v;
+            L[tri_idx(r, k)] = v;
         }
         __syncthreads();
         if (tau.x == 0.0 && tau.y == 0.0) continue;
-        // p = A22 v: rows split over thread groups, columns over the group's lanes
-        for (int r = k + 1 + tid / 2; r < n; r += kWgThreads / 2) {
+        // p = A22 v: rows over thread pairs, the pair's two threads over alternate columns
+        for (int r = k + 1 + (tid >> 1); r < n; r += kWgThreads / 2) {
             double2 p = c_make(0.0, 0.0);
-            for (int c = k + 1 + (tid & 1); c < n; c += 2) p = c_fma(P[r * n + c], S.vv[c], p);
+            const int rb = tri_idx(r, 0);
+            for (int c = k + 1 + (tid & 1); c < n; c += 2) {
+                const double2 a = (c <= r) ? L[rb + c] : c_conj(L[tri_idx(c, r)]);
+                p = c_fma(a, S.vv[c], p);
+            }
             p.x += __shfl_xor(p.x, 1, 64);
             p.y += __shfl_xor(p.y, 1, 64);
             if ((tid & 1) == 0) S.wv[r] = p;
@@ -278,17 +328,30 @@ __device__ void wg_tridiag(WgLds& S, double2* __restrict__ P, int n) {
         for (int r = k + 1 + tid; r < n; r += kWgThreads)
             S.wv[r] = c_sub(c_mul(tau, S.wv[r]), c_scale(t2, S.vv[r]));
         __syncthreads();
-        for (int e = tid; e < m * m; e += kWgThreads) {
-            const int r = k + 1 + e / m, c = k + 1 + (e - (e / m) * m);
-            double2 a = P[r * n + c];
-            a = c_rank2c(a, S.vv[r], S.wv[c], S.wv[r], S.vv[c]);
-            P[r * n + c] = a;
+        // trailing lower triangle: lanes over the columns c (a row's elements are
+        // consecutive), the two halves of the workgroup over alternate rows r >= c
+        {
+            const int c = k + 1 + (tid & 127), h = tid >> 7;
+            const double2 vc = (c < n) ? S.vv[c] : c_make(0.0, 0.0);
+            const double2 wc = (c < n) ? S.wv[c] : c_make(0.0, 0.0);
+            for (int r = k + 1 + h; r < n; r += 2) {
+                if (c <= r) {
+                    const int ix = tri_idx(r, c);
+                    L[ix] = c_rank2c(L[ix], S.vv[r], wc, S.wv[r], vc);
+                }
+            }
         }
         __syncthreads();
     }
     if (tid == 0) {
-        S.d[n - 1] = P[(n - 1) * n + (n - 1)].x;
+        S.d[n - 1] = L[tri_idx(n - 1, n - 1)].x;
         S.e[n - 1] = 0.0;
+    }
+    // the reflectors back to P, column k below the diagonal
+    for (int e = tid; e < nt; e += kWgThreads) {
+        const int r = tri_row(e);
+        const int c = e - tri_idx(r, 0);
+        if (c < r) P[r * n + c] = L[e];
     }
     __syncthreads();
 }
@@ -536,61 +599,69 @@ __device__ void wg_bisect(WgLds& S, int n, double& pivmin_out, double& span_out)
 // step 2c: eigenvectors of T by twisted factorisations, Z -> U (real parts)
 // thread j owns eigenvector j; pivots go to DPM in [i][j] order (coalesced)
 // ---------------------------------------------------------------------------
-__device__ void wg_twisted(WgLds& S, const WgScratch& X, int n, double pivmin) {
-    const int j = threadIdx.x;
-    const long long nn = (long long)n * n;
+__device__ void wg_twisted(WgLds& S, const WgScratch& X, int n, double pivmin, double* __restrict__ R,
+                           size_t r_doubles) {
+    // the pivots of G eigenvectors at a time in the LDS region R: dp[i][t] at R[i G + t],
+    // dm[i][t] at R[(n + i) G + t] (consecutive threads, consecutive words)
+    const int Gmax = (int)(r_doubles / (2 * (size_t)n));
+    const int G = Gmax < n ? Gmax : n;
     // reciprocal: hardware estimate and one Newton step (|q| >= pivmin keeps it finite)
     auto rcp = [](double q) {
         const double r0 = __builtin_amdgcn_rcp(q);
         return fma(r0, fma(-q, r0, 1.0), r0);
     };
-    if (j < n) {
-        const double lam = S.lam[j];
-        double* dp = X.DPM;
-        double* dm = X.DPM + nn;
-        double qv = 1.0, e2prev = 0.0;
-        for (int i = 0; i < n; ++i) {
-            double qi = (S.d[i] - lam) - e2prev * rcp(qv);
-            if (fabs(qi) < pivmin) qi = -pivmin;
-            dp[(long long)i * n + j] = qi;
-            qv = qi;
-            e2prev = S.e[i] * S.e[i];
-        }
-        qv = 1.0;
-        int r = 0;
-        double best = 1e308, gam = 0.0;
-        for (int i = n - 1; i >= 0; --i) {
-            double qi = (S.d[i] - lam) - ((i < n - 1) ? S.e[i] * S.e[i] * rcp(qv) : 0.0);
-            if (fabs(qi) < pivmin) qi = -pivmin;
-            dm[(long long)i * n + j] = qi;
-            qv = qi;
-            const double g = dp[(long long)i * n + j] + qi - (S.d[i] - lam);
-            if (fabs(g) < best) {
-                best = fabs(g);
-                gam = g;
-                r = i;
+    for (int g0 = 0; g0 < n; g0 += G) {
+        const int t = threadIdx.x, j = g0 + t;
+        if (t < G && j < n) {
+            const double lam = S.lam[j];
+            double* dp = R + t;
+            double* dm = R + (size_t)n * G + t;
+            double qv = 1.0, e2prev = 0.0;
+            for (int i = 0; i < n; ++i) {
+                double qi = (S.d[i] - lam) - e2prev * rcp(qv);
+                if (fabs(qi) < pivmin) qi = -pivmin;
+                dp[i * G] = qi;
+                qv = qi;
+                e2prev = S.e[i] * S.e[i];
             }
+            qv = 1.0;
+            int r = 0;
+            double best = 1e308, gam = 0.0;
+            for (int i = n - 1; i >= 0; --i) {
+                double qi = (S.d[i] - lam) - ((i < n - 1) ? S.e[i] * S.e[i] * rcp(qv) : 0.0);
+                if (fabs(qi) < pivmin) qi = -pivmin;
+                dm[i * G] = qi;
+                qv = qi;
+                const double g = dp[i * G] + qi - (S.d[i] - lam);
+                if (fabs(g) < best) {
+                    best = fabs(g);
+                    gam = g;
+                    r = i;
+                }
+            }
+            double nrm = 1.0;
+            double z = 1.0;
+            for (int i = r - 1; i >= 0; --i) {
+                z = -(S.e[i] * rcp(dp[i * G])) * z;
+                dp[i * G] = z;  // the pivot is spent: keep z_i in its place
+                nrm += z * z;
+            }
+            z = 1.0;
+            for (int i = r + 1; i < n; ++i) {
+                z = -(S.e[i - 1] * rcp(dm[i * G])) * z;
+                dm[i * G] = z;
+                nrm += z * z;
+            }
+            const double inv = 1.0 / sqrt(nrm);
+            for (int i = 0; i < n; ++i) {
+                const double zi = (i < r) ? dp[i * G] : ((i == r) ? 1.0 : dm[i * G]);
+                X.U[(long long)i * n + j] = c_make(zi * inv, 0.0);
+            }
+            // (T - lam) z = gam e_r with z_r = 1: Rayleigh-quotient correction
+            S.E[j] = lam + gam / nrm;
         }
-        double nrm = 1.0;
-        X.U[(long long)r * n + j] = c_make(1.0, 0.0);
-        double z = 1.0;
-        for (int i = r - 1; i >= 0; --i) {
-            z = -(S.e[i] * rcp(dp[(long long)i * n + j])) * z;
-            X.U[(long long)i * n + j] = c_make(z, 0.0);
-            nrm += z * z;
-        }
-        z = 1.0;
-        for (int i = r + 1; i < n; ++i) {
-            z = -(S.e[i - 1] * rcp(dm[(long long)i * n + j])) * z;
-            X.U[(long long)i * n + j] = c_make(z, 0.0);
-            nrm += z * z;
-        }
-        const double inv = 1.0 / sqrt(nrm);
-        for (int i = 0; i < n; ++i) X.U[(long long)i * n + j].x *= inv;
-        // (T - lam) z = gam e_r with z_r = 1: Rayleigh-quotient correction
-        S.E[j] = lam + gam / nrm;
+        __syncthreads();
     }
-    __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -693,98 +764,73 @@ __device__ bool wg_ql(WgLds& S, double2* __restrict__ Z, int n, int max_iter) {
 }
 
 // ---------------------------------------------------------------------------
-// step 2d: U <- H_0 ... H_{n-2} U.  G consecutive threads share a column
-// (G = the largest power of two with G n <= 256), each taking every G-th row;
-// the reflector is staged in LDS once per step and the partial products are
-// combined across the G lanes.
+// step 2d: U <- H_0 ... H_{n-2} U with U's column c in registers, four threads
+// per column (rows 4 jj + g), 64 columns per pass (one pass for n <= 64, two
+// for n <= 128), the reflectors staged into LDS sixteen columns at a time, and
+// groups of four row slots that lie above the reflector skipped by a
+// wave-uniform test.  No global traffic but one read and one write of U.
 // ---------------------------------------------------------------------------
-// n <= 64: U's column c in registers, four threads per column (rows 4 jj + g),
-// the reflectors staged into LDS sixteen columns at a time, and groups of four
-// row slots that lie above the reflector skipped by a wave-uniform test.
+template <int NR>
 __device__ void wg_backtransform_reg(WgLds& S, const double2* __restrict__ P, double2* __restrict__ U,
                                      int n) {
-    constexpr int G = 4, RJ = 16, KC = 16;
+    // NR = 64 or 128 rows at most: four threads per column (a DPP quad), each holding the
+    // rows g, g + 4, ... of its column in registers; 64 columns per pass
+    constexpr int G = 4, RJ = NR / G, KC = 16;
     const int tid = threadIdx.x;
-    const int c = tid >> 2, g = tid & 3;
-    const bool act = c < n;
-    double2* V = S.ta;  // [KC][64]: reflector columns k0 .. k0+KC-1
-    double2 u[RJ];
+    double2* V = S.ta;  // [KC][NR]: reflector columns k0 .. k0+KC-1 (the LDS scratch region)
+    for (int c0 = 0; c0 < n; c0 += kWgThreads / G) {
+        const int c = c0 + (tid >> 2), g = tid & 3;
+        const bool act = c < n;
+        double2 u[RJ];
 #pragma unroll
-    for (int jj = 0; jj < RJ; ++jj) {
-        const int r = G * jj + g;
-        u[jj] = (act && r < n) ? U[r * n + c] : c_make(0.0, 0.0);
-    }
-    for (int k1 = n - 1; k1 > 0; k1 -= KC) {
-        const int k0 = (k1 - KC > 0) ? k1 - KC : 0;  // this chunk: reflectors k0 .. k1-1
-        __syncthreads();
-        for (int e = tid; e < (k1 - k0) * 64; e += kWgThreads) {
-            const int kk = e >> 6, r = e & 63;
-            const int k = k0 + kk;
-            V[kk * 64 + r] = (r > k && r < n) ? P[r * n + k] : c_make(0.0, 0.0);
+        for (int jj = 0; jj < RJ; ++jj) {
+            const int r = G * jj + g;
+            u[jj] = (act && r < n) ? U[r * n + c] : c_make(0.0, 0.0);
         }
-        __syncthreads();
-        for (int k = k1 - 1; k >= k0; --k) {
-            const double2 tau = S.tau[k];
-            if (tau.x == 0.0 && tau.y == 0.0) continue;
-            const double2* v = V + (k - k0) * 64;
-            double2 y = c_make(0.0, 0.0);
-#pragma unroll
-            for (int gq = 0; gq < RJ / 4; ++gq) {
-                if (16 * gq + 15 > k) {
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) y = c_fmac(v[G * (4 * gq + t) + g], u[4 * gq + t], y);
-                }
+        for (int k1 = n - 1; k1 > 0; k1 -= KC) {
+            const int k0 = (k1 - KC > 0) ? k1 - KC : 0;  // this chunk: reflectors k0 .. k1-1
+            __syncthreads();
+            for (int e = tid; e < (k1 - k0) * NR; e += kWgThreads) {
+                const int kk = e / NR, r = e - (e / NR) * NR;
+                const int k = k0 + kk;
+                V[kk * NR + r] = (r > k && r < n) ? P[r * n + k] : c_make(0.0, 0.0);
             }
-            // the column's four threads are a DPP quad
-            y.x += __builtin_amdgcn_update_dpp(0.0, y.x, 0xB1, 0xF, 0xF, false);
-            y.y += __builtin_amdgcn_update_dpp(0.0, y.y, 0xB1, 0xF, 0xF, false);
-            y.x += __builtin_amdgcn_update_dpp(0.0, y.x, 0x4E, 0xF, 0xF, false);
-            y.y += __builtin_amdgcn_update_dpp(0.0, y.y, 0x4E, 0xF, 0xF, false);
-            const double2 ty = c_mul(tau, y);
+            __syncthreads();
+            for (int k = k1 - 1; k >= k0; --k) {
+                const double2 tau = S.tau[k];
+                if (tau.x == 0.0 && tau.y == 0.0) continue;
+                const double2* v = V + (k - k0) * NR;
+                double2 y = c_make(0.0, 0.0);
 #pragma unroll
-            for (int gq = 0; gq < RJ / 4; ++gq) {
-                if (16 * gq + 15 > k) {
+                for (int gq = 0; gq < RJ / 4; ++gq) {
+                    if (16 * gq + 15 > k) {
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        const int jj = 4 * gq + t;
-                        u[jj] = c_fnma(v[G * jj + g], ty, u[jj]);
+                        for (int t = 0; t < 4; ++t) y = c_fmac(v[G * (4 * gq + t) + g], u[4 * gq + t], y);
+                    }
+                }
+                // the column's four threads are a DPP quad
+                y.x += __builtin_amdgcn_update_dpp(0.0, y.x, 0xB1, 0xF, 0xF, false);
+                y.y += __builtin_amdgcn_update_dpp(0.0, y.y, 0xB1, 0xF, 0xF, false);
+                y.x += __builtin_amdgcn_update_dpp(0.0, y.x, 0x4E, 0xF, 0xF, false);
+                y.y += __builtin_amdgcn_update_dpp(0.0, y.y, 0x4E, 0xF, 0xF, false);
+                const double2 ty = c_mul(tau, y);
+#pragma unroll
+                for (int gq = 0; gq < RJ / 4; ++gq) {
+                    if (16 * gq + 15 > k) {
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            const int jj = 4 * gq + t;
+                            u[jj] = c_fnma(v[G * jj + g], ty, u[jj]);
+                        }
                     }
                 }
             }
         }
-    }
-    __syncthreads();
 #pragma unroll
-    for (int jj = 0; jj < RJ; ++jj) {
-        const int r = G * jj + g;
-        if (act && r < n) U[r * n + c] = u[jj];
-    }
-    __syncthreads();
-}
-
-__device__ void wg_backtransform(WgLds& S, const double2* __restrict__ P, double2* __restrict__ U,
-                                 int n) {
-    int G = 1;
-    while (2 * G * n <= kWgThreads && G < 64) G *= 2;
-    const int tid = threadIdx.x;
-    const int c = tid / G, g = tid - c * G;
-    const bool act = c < n;
-    for (int k = n - 2; k >= 0; --k) {
-        const double2 tau = S.tau[k];
-        if (tau.x == 0.0 && tau.y == 0.0) continue;
-        for (int r = k + 1 + tid; r < n; r += kWgThreads) S.vv[r] = P[r * n + k];
-        __syncthreads();
-        double2 y = c_make(0.0, 0.0);
-        if (act)
-            for (int r = k + 1 + g; r < n; r += G) y = c_fmac(S.vv[r], U[r * n + c], y);
-        for (int off = 1; off < G; off <<= 1) {
-            y.x += __shfl_xor(y.x, off, 64);
-            y.y += __shfl_xor(y.y, off, 64);
+        for (int jj = 0; jj < RJ; ++jj) {
+            const int r = G * jj + g;
+            if (act && r < n) U[r * n + c] = u[jj];
         }
-        const double2 ty = c_mul(tau, y);
-        if (act)
-            for (int r = k + 1 + g; r < n; r += G) U[r * n + c] = c_fnma(S.vv[r], ty, U[r * n + c]);
-        __syncthreads();
     }
     __syncthreads();
 }
@@ -923,29 +969,26 @@ __device__ bool wg_eigen_velocities(WgLds& S, const WgScratch& X, const ModelDev
         for (int e = threadIdx.x; e < n * n; e += kWgThreads) X.P[e] = Pl[e];
         __syncthreads();
     } else {
-        wg_tridiag(S, X.P, n);
+        wg_tridiag_packed(S, X.P, n, reinterpret_cast<double2*>(wg_region(S)));
     }
     double pivmin, span;
     wg_bisect(S, n, pivmin, span);
     int close = 0;
     for (int j = threadIdx.x; j < n - 1; j += kWgThreads)
-        if (S.lam[j + 1] - S.lam[j] < 1e-3 * span) close = 1;
+        if (S.lam[j + 1] - S.lam[j] < kWgClusterGap * span) close = 1;
     if (threadIdx.x == 0) S.flag = 0;
     __syncthreads();
     if (close) S.flag = 1;
     __syncthreads();
     bool ok = true;
     if (S.flag == 0 && max_iter > 1) {
-        wg_twisted(S, X, n, pivmin);
+        wg_twisted(S, X, n, pivmin, wg_region(S), wg_region_doubles<SMALL>());
         for (int j = threadIdx.x; j < n; j += kWgThreads)
             if (!isfinite(S.E[j])) ok = false;
     } else {
         ok = wg_ql(S, X.U, n, max_iter);
     }
-    if constexpr (SMALL)
-        wg_backtransform_reg(S, X.P, X.U, n);
-    else
-        wg_backtransform(S, X.P, X.U, n);
+    wg_backtransform_reg<SMALL ? 64 : 128>(S, X.P, X.U, n);
     const double2* U = X.U;
     double2* W = X.W;
     double2* VX = X.VX;
@@ -1123,19 +1166,29 @@ __global__ __launch_bounds__(kWgThreads, SMALL ? 2 : 1) void k_adjoint_wg(WgLaun
                 X.K[e] = k;
             }
             __syncthreads();
-            // Hbar' (into W)
+            // Hbar'_mq = X_mq / (E_m - E_q) with X = (i/N)(D + D^+), D = (K o B) A - (K o A) B
+            // (two products, W and P); on the diagonal and for pairs closer than delta the
+            // divided-difference limit (i/N) sum_p dK(x, E_p)/dx (B_mp A_pq - A_mp B_pq) at
+            // x = (E_m + E_q)/2.  Hbar' goes to HB (the pivot region, dead by now).
+            const double2* U = X.U;
+            double2* P = X.P;
+            double2* W = X.W;
+            double2* VX = X.VX;
+            double2* VY = X.VY;
+            const double* K = X.K;
+            double2* HB = reinterpret_cast<double2*>(X.DPM);
+            wg_gemm<SMALL>(S, W, n, [=](int i, int k) { return c_scale(K[i * n + k], VY[i * n + k]); },
+                    [=](int k, int j) { return VX[k * n + j]; });
+            wg_gemm<SMALL>(S, P, n, [=](int i, int k) { return c_scale(K[i * n + k], VX[i * n + k]); },
+                    [=](int k, int j) { return VY[k * n + j]; });
             for (int e = threadIdx.x; e < n * n; e += kWgThreads) {
                 const int m = e / n, q = e - (e / n) * n;
                 const double de = S.E[m] - S.E[q];
                 double2 acc = c_make(0.0, 0.0);
                 if (m != q && fabs(de) >= delta) {
-                    for (int p = 0; p < n; ++p) {
-                        const double w = X.K[m * n + p] - X.K[q * n + p];
-                        double2 z = c_mul(B[m * n + p], A[p * n + q]);
-                        z = c_fnma(A[m * n + p], B[p * n + q], z);
-                        acc = c_add(acc, c_scale(w, z));
-                    }
-                    acc = c_scale(invN / de, c_i(acc));
+                    const double2 dmq = c_sub(W[m * n + q], P[m * n + q]);
+                    const double2 dqm = c_sub(W[q * n + m], P[q * n + m]);
+                    acc = c_scale(invN / de, c_i(c_add(dmq, c_conj(dqm))));
                 } else {
                     const double xm = 0.5 * (S.E[m] + S.E[q]);
                     double phx, dphx;
@@ -1155,17 +1208,11 @@ __global__ __launch_bounds__(kWgThreads, SMALL ? 2 : 1) void k_adjoint_wg(WgLaun
                     }
                     acc = c_scale(invN, c_i(acc));
                 }
-                X.W[e] = acc;
+                HB[e] = acc;
             }
             __syncthreads();
-            const double2* U = X.U;
-            double2* P = X.P;
-            double2* W = X.W;
-            double2* VX = X.VX;
-            double2* VY = X.VY;
-            const double* K = X.K;
             // Hbar = U Hbar' U^+  (P = Hbar' U^+, W = U P)
-            wg_gemm<SMALL>(S, P, n, [=](int i, int k) { return W[i * n + k]; },
+            wg_gemm<SMALL>(S, P, n, [=](int i, int k) { return HB[i * n + k]; },
                     [=](int k, int j) { return c_conj(U[j * n + k]); });
             wg_gemm<SMALL>(S, W, n, [=](int i, int k) { return U[i * n + k]; },
                     [=](int k, int j) { return P[k * n + j]; });
@@ -1210,7 +1257,7 @@ static hipError_t wg_attrs() {
                          reinterpret_cast<const void*>(&k_adjoint_wg<true>),
                          reinterpret_cast<const void*>(&k_adjoint_wg<false>)};
     for (const void* f : fns) {
-        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kWgSmallLds);
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kWgBigLds);
         if (e != hipSuccess) return e;
     }
     g_wg_attr = true;
@@ -1231,9 +1278,9 @@ hipError_t launch_forward_wg(const WgLaunch& L, int np, hipStream_t s) {
             hipLaunchKernelGGL((k_forward_wg<true, false>), dim3(grid), dim3(kWgThreads), kWgSmallLds, s, L);
     } else {
         if (L.tensor)
-            hipLaunchKernelGGL((k_forward_wg<false, true>), dim3(grid), dim3(kWgThreads), sizeof(WgLds), s, L);
+            hipLaunchKernelGGL((k_forward_wg<false, true>), dim3(grid), dim3(kWgThreads), kWgBigLds, s, L);
         else
-            hipLaunchKernelGGL((k_forward_wg<false, false>), dim3(grid), dim3(kWgThreads), sizeof(WgLds), s, L);
+            hipLaunchKernelGGL((k_forward_wg<false, false>), dim3(grid), dim3(kWgThreads), kWgBigLds, s, L);
     }
     return hipGetLastError();
 }
@@ -1246,7 +1293,7 @@ hipError_t launch_adjoint_wg(const WgLaunch& L, int np, hipStream_t s) {
     if (np <= 64)
         hipLaunchKernelGGL(k_adjoint_wg<true>, dim3(grid), dim3(kWgThreads), kWgSmallLds, s, L);
     else
-        hipLaunchKernelGGL(k_adjoint_wg<false>, dim3(grid), dim3(kWgThreads), sizeof(WgLds), s, L);
+        hipLaunchKernelGGL(k_adjoint_wg<false>, dim3(grid), dim3(kWgThreads), kWgBigLds, s, L);
     return hipGetLastError();
 }
 
