@@ -308,14 +308,28 @@ __device__ void wg_tridiag_packed(WgLds& S, double2* __restrict__ P, int n, doub
         }
         __syncthreads();
         if (tau.x == 0.0 && tau.y == 0.0) continue;
-        // p = A22 v: rows over thread pairs, the pair's two threads over alternate columns
+        // p = A22 v: rows over thread pairs, the pair's two threads over alternate
+        // columns; the row part (c <= r, consecutive words) and the column part (c > r,
+        // the conjugate of row c) as separate loops, four independent sums each
         for (int r = k + 1 + (tid >> 1); r < n; r += kWgThreads / 2) {
-            double2 p = c_make(0.0, 0.0);
+            double2 p0 = c_make(0.0, 0.0), p1 = p0, p2 = p0, p3 = p0;
             const int rb = tri_idx(r, 0);
-            for (int c = k + 1 + (tid & 1); c < n; c += 2) {
-                const double2 a = (c <= r) ? L[rb + c] : c_conj(L[tri_idx(c, r)]);
-                p = c_fma(a, S.vv[c], p);
+            int c = k + 1 + (tid & 1);
+            for (; c + 6 <= r; c += 8) {
+                p0 = c_fma(L[rb + c], S.vv[c], p0);
+                p1 = c_fma(L[rb + c + 2], S.vv[c + 2], p1);
+                p2 = c_fma(L[rb + c + 4], S.vv[c + 4], p2);
+                p3 = c_fma(L[rb + c + 6], S.vv[c + 6], p3);
             }
+            for (; c <= r; c += 2) p0 = c_fma(L[rb + c], S.vv[c], p0);
+            for (; c + 6 < n; c += 8) {
+                p0 = c_fmac(L[tri_idx(c, r)], S.vv[c], p0);
+                p1 = c_fmac(L[tri_idx(c + 2, r)], S.vv[c + 2], p1);
+                p2 = c_fmac(L[tri_idx(c + 4, r)], S.vv[c + 4], p2);
+                p3 = c_fmac(L[tri_idx(c + 6, r)], S.vv[c + 6], p3);
+            }
+            for (; c < n; c += 2) p0 = c_fmac(L[tri_idx(c, r)], S.vv[c], p0);
+            double2 p = c_add(c_add(p0, p1), c_add(p2, p3));
             p.x += __shfl_xor(p.x, 1, 64);
             p.y += __shfl_xor(p.y, 1, 64);
             if ((tid & 1) == 0) S.wv[r] = p;
@@ -334,7 +348,18 @@ __device__ void wg_tridiag_packed(WgLds& S, double2* __restrict__ P, int n, doub
             const int c = k + 1 + (tid & 127), h = tid >> 7;
             const double2 vc = (c < n) ? S.vv[c] : c_make(0.0, 0.0);
             const double2 wc = (c < n) ? S.wv[c] : c_make(0.0, 0.0);
-            for (int r = k + 1 + h; r < n; r += 2) {
+            int r = k + 1 + h;
+            for (; r + 6 < n; r += 8) {
+                double2 x[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (c <= r + 2 * u) x[u] = L[tri_idx(r + 2 * u, c)];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (c <= r + 2 * u)
+                        L[tri_idx(r + 2 * u, c)] = c_rank2c(x[u], S.vv[r + 2 * u], wc, S.wv[r + 2 * u], vc);
+            }
+            for (; r < n; r += 2) {
                 if (c <= r) {
                     const int ix = tri_idx(r, c);
                     L[ix] = c_rank2c(L[ix], S.vv[r], wc, S.wv[r], vc);
@@ -943,12 +968,92 @@ __device__ void wg_gemm_tiles(WgLds& S, double2* __restrict__ C, int n, FA LA, F
     __syncthreads();
 }
 
-template <bool MFMA, class FA, class FB>
+// C = A B with C n x n and an inner dimension nk (complex) on the FP64 matrix cores,
+// operands staged through LDS.  C is taken in 64 x 64 macro tiles; per panel of
+// kWgKT inner indices the workgroup copies A[64 rows][kWgKT] and B[kWgKT][64 cols]
+// into the LDS scratch region with coalesced global reads (A_IFAST: LA(i, k) is
+// contiguous in i in memory, else in k; B_KFAST: LB(k, j) contiguous in k, else in
+// j), then each wavefront accumulates its 32 x 32 block as 2 x 2 tiles of
+// v_mfma_f64_16x16x4 with separate real and imaginary accumulators (four real
+// products per complex one; eight independent accumulators).  Rows padded by one
+// element keep the operand reads free of bank conflicts.
+constexpr int kWgKT = 16;
+constexpr int kWgLdA = kWgKT + 1, kWgLdB = 64 + 1;
+template <bool A_IFAST, bool B_KFAST, class FA, class FB>
+__device__ void wg_gemm_lds(WgLds& S, double2* __restrict__ C, int n, int nk, FA LA, FB LB) {
+    double2* As = S.ta;                // [64][kWgLdA]
+    double2* Bs = S.ta + 64 * kWgLdA;  // [kWgKT][kWgLdB]
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int g = lane >> 4, c = lane & 15;
+    const int wr = w >> 1, wc = w & 1;
+    const wg_v4d zero = {0.0, 0.0, 0.0, 0.0};
+    const int nmt = (n + 63) >> 6;
+    for (int mt = 0; mt < nmt * nmt; ++mt) {
+        const int i0 = 64 * (mt / nmt), j0 = 64 * (mt - (mt / nmt) * nmt);
+        wg_v4d cr[2][2], ci[2][2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                cr[a][b] = zero;
+                ci[a][b] = zero;
+            }
+        for (int kb = 0; kb < nk; kb += kWgKT) {
+            __syncthreads();
+            for (int e = tid; e < 64 * kWgKT; e += kWgThreads) {
+                const int ii = A_IFAST ? (e & 63) : (e / kWgKT);
+                const int kk = A_IFAST ? (e >> 6) : (e - (e / kWgKT) * kWgKT);
+                const int gi = i0 + ii, gk = kb + kk;
+                As[ii * kWgLdA + kk] = (gi < n && gk < nk) ? LA(gi, gk) : c_make(0.0, 0.0);
+                const int jj = B_KFAST ? (e / kWgKT) : (e & 63);
+                const int k2 = B_KFAST ? (e - (e / kWgKT) * kWgKT) : (e >> 6);
+                const int gj = j0 + jj, gk2 = kb + k2;
+                Bs[k2 * kWgLdB + jj] = (gk2 < nk && gj < n) ? LB(gk2, gj) : c_make(0.0, 0.0);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k4 = 0; k4 < kWgKT / 4; ++k4) {
+                double2 av[2], bv[2];
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    av[t] = As[(32 * wr + 16 * t + c) * kWgLdA + 4 * k4 + g];
+                    bv[t] = Bs[(4 * k4 + g) * kWgLdB + 32 * wc + 16 * t + c];
+                }
+#pragma unroll
+                for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj < 2; ++tj) cr[ti][tj] = wg_mfma16(av[ti].x, bv[tj].x, cr[ti][tj]);
+#pragma unroll
+                for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj < 2; ++tj) ci[ti][tj] = wg_mfma16(av[ti].x, bv[tj].y, ci[ti][tj]);
+#pragma unroll
+                for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj < 2; ++tj) cr[ti][tj] = wg_mfma16(-av[ti].y, bv[tj].y, cr[ti][tj]);
+#pragma unroll
+                for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj < 2; ++tj) ci[ti][tj] = wg_mfma16(av[ti].y, bv[tj].x, ci[ti][tj]);
+            }
+        }
+#pragma unroll
+        for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+            for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int row = i0 + 32 * wr + 16 * ti + g + 4 * q, col = j0 + 32 * wc + 16 * tj + c;
+                    if (row < n && col < n) C[row * n + col] = c_make(cr[ti][tj][q], ci[ti][tj][q]);
+                }
+    }
+    __syncthreads();
+}
+
+// C = A B, n x n by n x n, for the orientation flags of wg_gemm_lds
+template <bool A_IFAST, bool B_KFAST, class FA, class FB>
 __device__ __forceinline__ void wg_gemm(WgLds& S, double2* __restrict__ C, int n, FA LA, FB LB) {
-    if constexpr (MFMA)
-        wg_gemm_mfma(S, C, n, LA, LB);
-    else
-        wg_gemm_tiles(S, C, n, LA, LB);
+    wg_gemm_lds<A_IFAST, B_KFAST>(S, C, n, n, LA, LB);
 }
 
 // Steps 1-3: E (S.E), U, and A = U^+ v_x U in X.VX, B = U^+ v_y U in X.VY.
@@ -993,13 +1098,13 @@ __device__ bool wg_eigen_velocities(WgLds& S, const WgScratch& X, const ModelDev
     double2* W = X.W;
     double2* VX = X.VX;
     double2* VY = X.VY;
-    wg_gemm<SMALL>(S, W, n, [=](int i, int k) { return VX[i * n + k]; },
+    wg_gemm<false, false>(S, W, n, [=](int i, int k) { return VX[i * n + k]; },
             [=](int k, int j) { return U[k * n + j]; });
-    wg_gemm<SMALL>(S, VX, n, [=](int i, int k) { return c_conj(U[k * n + i]); },
+    wg_gemm<true, false>(S, VX, n, [=](int i, int k) { return c_conj(U[k * n + i]); },
             [=](int k, int j) { return W[k * n + j]; });
-    wg_gemm<SMALL>(S, W, n, [=](int i, int k) { return VY[i * n + k]; },
+    wg_gemm<false, false>(S, W, n, [=](int i, int k) { return VY[i * n + k]; },
             [=](int k, int j) { return U[k * n + j]; });
-    wg_gemm<SMALL>(S, VY, n, [=](int i, int k) { return c_conj(U[k * n + i]); },
+    wg_gemm<true, false>(S, VY, n, [=](int i, int k) { return c_conj(U[k * n + i]); },
             [=](int k, int j) { return W[k * n + j]; });
     return ok;
 }
@@ -1041,14 +1146,14 @@ __global__ __launch_bounds__(kWgThreads, SMALL ? 2 : 1) void k_forward_wg(WgLaun
                 wg_build_tensor(S, md, T0, T2, r0, it.i0 + kk, spin, VZ, JS);
                 const double2* U = X.U;
                 double2* W = X.W;
-                wg_gemm<SMALL>(S, W, n, [=](int i, int k) { return VZ[i * n + k]; },
+                wg_gemm<false, false>(S, W, n, [=](int i, int k) { return VZ[i * n + k]; },
                         [=](int k, int j) { return U[k * n + j]; });
-                wg_gemm<SMALL>(S, VZ, n, [=](int i, int k) { return c_conj(U[k * n + i]); },
+                wg_gemm<true, false>(S, VZ, n, [=](int i, int k) { return c_conj(U[k * n + i]); },
                         [=](int k, int j) { return W[k * n + j]; });
                 if (spin) {
-                    wg_gemm<SMALL>(S, W, n, [=](int i, int k) { return JS[i * n + k]; },
+                    wg_gemm<false, false>(S, W, n, [=](int i, int k) { return JS[i * n + k]; },
                             [=](int k, int j) { return U[k * n + j]; });
-                    wg_gemm<SMALL>(S, JS, n, [=](int i, int k) { return c_conj(U[k * n + i]); },
+                    wg_gemm<true, false>(S, JS, n, [=](int i, int k) { return c_conj(U[k * n + i]); },
                             [=](int k, int j) { return W[k * n + j]; });
                 }
             }
@@ -1167,9 +1272,12 @@ __global__ __launch_bounds__(kWgThreads, SMALL ? 2 : 1) void k_adjoint_wg(WgLaun
             }
             __syncthreads();
             // Hbar'_mq = X_mq / (E_m - E_q) with X = (i/N)(D + D^+), D = (K o B) A - (K o A) B
-            // (two products, W and P); on the diagonal and for pairs closer than delta the
-            // divided-difference limit (i/N) sum_p dK(x, E_p)/dx (B_mp A_pq - A_mp B_pq) at
-            // x = (E_m + E_q)/2.  Hbar' goes to HB (the pivot region, dead by now).
+            // and D^+ = B (K o A) - A (K o B) (K is real and antisymmetric, A and B are
+            // Hermitian): two products with an inner dimension of 2n, [K o B, -K o A][A; B]
+            // into W and [A, B][-K o B; K o A] into P.  On the diagonal and for pairs closer
+            // than delta the divided-difference limit (i/N) sum_p dK(x, E_p)/dx
+            // (B_mp A_pq - A_mp B_pq) at x = (E_m + E_q)/2.  Hbar' goes to HB (the pivot
+            // region, dead by now).
             const double2* U = X.U;
             double2* P = X.P;
             double2* W = X.W;
@@ -1177,54 +1285,71 @@ __global__ __launch_bounds__(kWgThreads, SMALL ? 2 : 1) void k_adjoint_wg(WgLaun
             double2* VY = X.VY;
             const double* K = X.K;
             double2* HB = reinterpret_cast<double2*>(X.DPM);
-            wg_gemm<SMALL>(S, W, n, [=](int i, int k) { return c_scale(K[i * n + k], VY[i * n + k]); },
-                    [=](int k, int j) { return VX[k * n + j]; });
-            wg_gemm<SMALL>(S, P, n, [=](int i, int k) { return c_scale(K[i * n + k], VX[i * n + k]); },
-                    [=](int k, int j) { return VY[k * n + j]; });
+            wg_gemm_lds<false, false>(S, W, n, 2 * n,
+                    [=](int i, int k) {
+                        return k < n ? c_scale(K[i * n + k], VY[i * n + k])
+                                     : c_scale(-K[i * n + k - n], VX[i * n + k - n]);
+                    },
+                    [=](int k, int j) { return k < n ? VX[k * n + j] : VY[(k - n) * n + j]; });
+            wg_gemm_lds<false, false>(S, P, n, 2 * n,
+                    [=](int i, int k) { return k < n ? VX[i * n + k] : VY[i * n + k - n]; },
+                    [=](int k, int j) {
+                        return k < n ? c_scale(-K[k * n + j], VY[k * n + j])
+                                     : c_scale(K[(k - n) * n + j], VX[(k - n) * n + j]);
+                    });
             for (int e = threadIdx.x; e < n * n; e += kWgThreads) {
                 const int m = e / n, q = e - (e / n) * n;
                 const double de = S.E[m] - S.E[q];
-                double2 acc = c_make(0.0, 0.0);
-                if (m != q && fabs(de) >= delta) {
-                    const double2 dmq = c_sub(W[m * n + q], P[m * n + q]);
-                    const double2 dqm = c_sub(W[q * n + m], P[q * n + m]);
-                    acc = c_scale(invN / de, c_i(c_add(dmq, c_conj(dqm))));
-                } else {
-                    const double xm = 0.5 * (S.E[m] + S.E[q]);
-                    double phx, dphx;
-                    if (m == q) {
-                        phx = S.phi[m];
-                        dphx = S.dphi[m];
-                    } else {
-                        wg_phi_at(xm, ef, sb, a.nF, a.kT, phx, dphx);
+                HB[e] = (m != q && fabs(de) >= delta) ? c_scale(invN / de, c_i(c_add(W[e], P[e])))
+                                                      : c_make(0.0, 0.0);
+            }
+            // the diagonal and the pairs closer than delta (neighbours in the sorted
+            // spectrum): one wavefront per element, lanes over p
+            {
+                const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+                for (int m = wv; m < n; m += kWgThreads / 64) {
+                    int qlo = m, qhi = m;
+                    while (qlo > 0 && fabs(S.E[m] - S.E[qlo - 1]) < delta) --qlo;
+                    while (qhi < n - 1 && fabs(S.E[qhi + 1] - S.E[m]) < delta) ++qhi;
+                    for (int q = qlo; q <= qhi; ++q) {
+                        const double xm = 0.5 * (S.E[m] + S.E[q]);
+                        double phx, dphx;
+                        if (m == q) {
+                            phx = S.phi[m];
+                            dphx = S.dphi[m];
+                        } else {
+                            wg_phi_at(xm, ef, sb, a.nF, a.kT, phx, dphx);
+                        }
+                        double2 acc = c_make(0.0, 0.0);
+                        for (int p = lane; p < n; p += 64) {
+                            const double x = xm - S.E[p];
+                            const double den = x * x + eta2;
+                            const double w = dphx / den - (phx - S.phi[p]) * 2.0 * x / (den * den);
+                            double2 z = c_mul(B[m * n + p], A[p * n + q]);
+                            z = c_fnma(A[m * n + p], B[p * n + q], z);
+                            acc = c_add(acc, c_scale(w, z));
+                        }
+                        acc.x = wg_wave_reduce(acc.x, [](double x, double y) { return x + y; });
+                        acc.y = wg_wave_reduce(acc.y, [](double x, double y) { return x + y; });
+                        if (lane == 0) HB[m * n + q] = c_scale(invN, c_i(acc));
                     }
-                    for (int p = 0; p < n; ++p) {
-                        const double x = xm - S.E[p];
-                        const double den = x * x + eta2;
-                        const double w = dphx / den - (phx - S.phi[p]) * 2.0 * x / (den * den);
-                        double2 z = c_mul(B[m * n + p], A[p * n + q]);
-                        z = c_fnma(A[m * n + p], B[p * n + q], z);
-                        acc = c_add(acc, c_scale(w, z));
-                    }
-                    acc = c_scale(invN, c_i(acc));
                 }
-                HB[e] = acc;
             }
             __syncthreads();
             // Hbar = U Hbar' U^+  (P = Hbar' U^+, W = U P)
-            wg_gemm<SMALL>(S, P, n, [=](int i, int k) { return HB[i * n + k]; },
+            wg_gemm<false, true>(S, P, n, [=](int i, int k) { return HB[i * n + k]; },
                     [=](int k, int j) { return c_conj(U[j * n + k]); });
-            wg_gemm<SMALL>(S, W, n, [=](int i, int k) { return U[i * n + k]; },
+            wg_gemm<false, false>(S, W, n, [=](int i, int k) { return U[i * n + k]; },
                     [=](int k, int j) { return P[k * n + j]; });
             // vbar_x = U Abar U^+, Abar = (i/N) K o B   (P = Abar U^+, VY = U P)
-            wg_gemm<SMALL>(S, P, n, [=](int i, int k) { return c_scale(invN * K[i * n + k], c_i(VY[i * n + k])); },
+            wg_gemm<false, true>(S, P, n, [=](int i, int k) { return c_scale(invN * K[i * n + k], c_i(VY[i * n + k])); },
                     [=](int k, int j) { return c_conj(U[j * n + k]); });
-            wg_gemm<SMALL>(S, VY, n, [=](int i, int k) { return U[i * n + k]; },
+            wg_gemm<false, false>(S, VY, n, [=](int i, int k) { return U[i * n + k]; },
                     [=](int k, int j) { return P[k * n + j]; });
             // vbar_y = U Bbar U^+, Bbar = -(i/N) K o A  (P = Bbar U^+, VX = U P)
-            wg_gemm<SMALL>(S, P, n, [=](int i, int k) { return c_scale(-invN * K[i * n + k], c_i(VX[i * n + k])); },
+            wg_gemm<false, true>(S, P, n, [=](int i, int k) { return c_scale(-invN * K[i * n + k], c_i(VX[i * n + k])); },
                     [=](int k, int j) { return c_conj(U[j * n + k]); });
-            wg_gemm<SMALL>(S, VX, n, [=](int i, int k) { return U[i * n + k]; },
+            wg_gemm<false, false>(S, VX, n, [=](int i, int k) { return U[i * n + k]; },
                     [=](int k, int j) { return P[k * n + j]; });
             for (long long e = threadIdx.x; e < (long long)md.nR0 * nn; e += kWgThreads) {
                 const int rho = (int)(e / nn);
