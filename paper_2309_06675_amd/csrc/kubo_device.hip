@@ -75,66 +75,76 @@ __global__ void k_hermproj(Tables tb, int n_models, long long total, const doubl
 }
 
 // ---------------------------------------------------------------------------
-// k_pencil: per (model, i1, i2) the rho-resolved partial Bloch sums
+// k_pencil: per (model, i1, i2) the rho-resolved partial Bloch sums, for a group
+// of up to kPencilGroup pencils of one model at a time: each thread owns one
+// matrix element, reads each hopping t'(R) of it once and accumulates it into
+// every pencil of the group (the group's phases sit in LDS, a tile of lattice
+// vectors at a time).  Grid: x = pencil group, y = tile of 256 matrix elements.
 // ---------------------------------------------------------------------------
 constexpr int kPencilThreads = 256;
-constexpr int kPencilPhaseTile = 512;
+constexpr int kPencilPhaseTile = 256;
 
-__global__ __launch_bounds__(kPencilThreads) void k_pencil(Tables tb, int item_begin,
+__global__ __launch_bounds__(kPencilThreads) void k_pencil(Tables tb, int group_begin,
                                                            const double2* __restrict__ tp,
                                                            double2* __restrict__ tbuf, bool with_z) {
-    __shared__ double2 sph[kPencilPhaseTile];
-    const PencilItem it = tb.pencils[item_begin + blockIdx.x];
-    const ModelDev md = tb.models[it.model];
+    __shared__ double2 sph[kPencilPhaseTile][kPencilGroup];
+    const PencilGroup grp = tb.pgroups[group_begin + blockIdx.x];
+    const PencilItem p0 = tb.pencils[grp.first];
+    const ModelDev md = tb.models[p0.model];
     const int n = md.n;
     const long long nn = (long long)n * n;
-    double2* T0 = tbuf + it.tbuf_off;
-    double2* T1 = T0 + (long long)md.nR0 * nn;
-    double2* T2 = T1 + (long long)md.nR0 * nn;
+    if ((long long)blockIdx.y * kPencilThreads >= nn) return;  // whole workgroup past the matrix
+    const long long e = (long long)blockIdx.y * kPencilThreads + threadIdx.x;
+    const bool act = e < nn;
+    const int cnt = grp.count;
     const int* gstart = tb.grp_start + md.gs_first;
     for (int rho = 0; rho < md.nR0; ++rho) {
         const int g0 = gstart[rho], g1 = gstart[rho + 1];
-        // elements handled by this thread: e = tid, tid + NT, ...  (accumulate over R tiles)
-        for (long long e0 = 0; e0 < nn; e0 += kPencilThreads * 4) {
-            double2 a0[4], a1[4], a2[4];
+        double2 a0[kPencilGroup], a1[kPencilGroup], a2[kPencilGroup];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) a0[u] = a1[u] = a2[u] = c_make(0.0, 0.0);
-            for (int gt = g0; gt < g1; gt += kPencilPhaseTile) {
-                const int gcount = min(kPencilPhaseTile, g1 - gt);
-                __syncthreads();
-                for (int g = threadIdx.x; g < gcount; g += kPencilThreads) {
-                    int gi = md.grp_first + gt + g;
-                    sph[g] = unit_phase2((long long)it.i1 * tb.grp_R1[gi], md.N1,
-                                         (long long)it.i2 * tb.grp_R2[gi], md.N2);
+        for (int q = 0; q < kPencilGroup; ++q) a0[q] = a1[q] = a2[q] = c_make(0.0, 0.0);
+        for (int gt = g0; gt < g1; gt += kPencilPhaseTile) {
+            const int gcount = min(kPencilPhaseTile, g1 - gt);
+            __syncthreads();
+            for (int idx = threadIdx.x; idx < gcount * kPencilGroup; idx += kPencilThreads) {
+                const int g = idx / kPencilGroup, q = idx - g * kPencilGroup;
+                const int gi = md.grp_first + gt + g;
+                double2 ph = c_make(0.0, 0.0);
+                if (q < cnt) {
+                    const PencilItem pi = tb.pencils[grp.first + q];
+                    ph = unit_phase2((long long)pi.i1 * tb.grp_R1[gi], md.N1,
+                                     (long long)pi.i2 * tb.grp_R2[gi], md.N2);
                 }
-                __syncthreads();
+                sph[g][q] = ph;
+            }
+            __syncthreads();
+            if (act) {
                 for (int g = 0; g < gcount; ++g) {
                     const int gi = md.grp_first + gt + g;
                     const int r = tb.grp_r[gi];
-                    const double ry = (double)tb.grp_R1[gi];
-                    const double2 ph = sph[g];
-                    const double2 phy = c_i(c_scale(ry, ph));
-                    const double2 phz = c_i(c_scale((double)tb.grp_R2[gi], ph));
-                    const double2* tr = tp + md.t_off + (long long)r * nn;
+                    const double ry = (double)tb.grp_R1[gi], rz = (double)tb.grp_R2[gi];
+                    const double2 v = tp[md.t_off + (long long)r * nn + e];
+                    const double2 vy = c_i(c_scale(ry, v)), vz = c_i(c_scale(rz, v));
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        long long e = e0 + threadIdx.x + (long long)u * kPencilThreads;
-                        if (e < nn) {
-                            double2 v = tr[e];
-                            a0[u] = c_fma(v, ph, a0[u]);
-                            a1[u] = c_fma(v, phy, a1[u]);
-                            if (with_z) a2[u] = c_fma(v, phz, a2[u]);
+                    for (int q = 0; q < kPencilGroup; ++q) {
+                        if (q < cnt) {
+                            const double2 ph = sph[g][q];
+                            a0[q] = c_fma(v, ph, a0[q]);
+                            a1[q] = c_fma(vy, ph, a1[q]);
+                            if (with_z) a2[q] = c_fma(vz, ph, a2[q]);
                         }
                     }
                 }
             }
+        }
+        if (act) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                long long e = e0 + threadIdx.x + (long long)u * kPencilThreads;
-                if (e < nn) {
-                    T0[(long long)rho * nn + e] = a0[u];
-                    T1[(long long)rho * nn + e] = a1[u];
-                    if (with_z) T2[(long long)rho * nn + e] = a2[u];
+            for (int q = 0; q < kPencilGroup; ++q) {
+                if (q < cnt) {
+                    double2* T0 = tbuf + tb.pencils[grp.first + q].tbuf_off;
+                    T0[(long long)rho * nn + e] = a0[q];
+                    T0[(long long)(md.nR0 + rho) * nn + e] = a1[q];
+                    if (with_z) T0[(long long)(2 * md.nR0 + rho) * nn + e] = a2[q];
                 }
             }
         }
@@ -327,9 +337,9 @@ __global__ __launch_bounds__(kPaccThreads) void k_pacc(Tables tb, int begin, con
     if ((long long)blockIdx.y * kPaccThreads >= nn) return;  // whole workgroup past this matrix
     const long long e = (long long)blockIdx.y * kPaccThreads + threadIdx.x;
     const bool act = e < nn;
-    // the per-k matrices are Hermitian and only their upper triangle is stored
+    // the per-k matrices are Hermitian: stored whole (xfull) or as their upper triangle
     const int em = act ? (int)(e / md.n) : 0, ec = act ? (int)(e - (long long)em * md.n) : 0;
-    const bool lower = em > ec;
+    const bool lower = !it.xfull && em > ec;
     const long long es = lower ? (long long)ec * md.n + em : e;
     const int nR0 = md.nR0;
     const int* r0 = tb.r0val + md.r0_first;
@@ -389,10 +399,11 @@ __global__ __launch_bounds__(kPaccThreads) void k_pacc(Tables tb, int begin, con
     }
 }
 
-hipError_t launch_pencil(const Tables& tb, int item_begin, int item_count, const double* tp,
-                         double* tbuf, bool with_z, hipStream_t s) {
-    if (item_count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pencil, dim3(item_count), dim3(kPencilThreads), 0, s, tb, item_begin,
+hipError_t launch_pencil(const Tables& tb, int group_begin, int group_count, long long max_nn,
+                         const double* tp, double* tbuf, bool with_z, hipStream_t s) {
+    if (group_count <= 0) return hipSuccess;
+    const unsigned ty = (unsigned)((max_nn + kPencilThreads - 1) / kPencilThreads);
+    hipLaunchKernelGGL(k_pencil, dim3(group_count, ty), dim3(kPencilThreads), 0, s, tb, group_begin,
                        reinterpret_cast<const double2*>(tp), reinterpret_cast<double2*>(tbuf),
                        with_z);
     return hipGetLastError();

@@ -47,6 +47,7 @@ struct ClassRange {
 
 struct Chunk {
     int pencil_begin = 0, pencil_count = 0;
+    int pgroup_begin = 0, pgroup_count = 0;
     int grange_begin = 0, grange_count = 0;
     ClassRange cls[kNumClasses];
     long long cls_kpts[kNumClasses] = {0};
@@ -91,11 +92,12 @@ struct kubo_plan_s {
     // chunkings of the same k-blocks
     struct ChunkSet {
         std::vector<PencilItem> pencils;
+        std::vector<PencilGroup> pgroups;
         std::vector<BlockItem> blocks;
         std::vector<GaccRange> granges;
         std::vector<Chunk> chunks;
         size_t max_t = 0, max_p = 0, max_x = 0;
-        size_t tab_pencils = 0, tab_blocks = 0, tab_granges = 0;
+        size_t tab_pencils = 0, tab_pgroups = 0, tab_blocks = 0, tab_granges = 0;
     } fwd, bwd;
     int n_slots = 0;
     int n_orb_total = 0;    // orbitals summed over the models (length of a spin array)
@@ -140,6 +142,7 @@ Tables device_tables(const kubo_plan_s* p, unsigned char* ws, bool backward) {
     t.negr = reinterpret_cast<const int*>(b + p->tab_off[6]);
     t.grp_rho = reinterpret_cast<const int*>(b + p->tab_off[9]);
     t.pencils = reinterpret_cast<const PencilItem*>(b + cs.tab_pencils);
+    t.pgroups = reinterpret_cast<const PencilGroup*>(b + cs.tab_pgroups);
     t.blocks = reinterpret_cast<const BlockItem*>(b + cs.tab_blocks);
     t.granges = reinterpret_cast<const GaccRange*>(b + cs.tab_granges);
     return t;
@@ -175,7 +178,7 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
         std::vector<BlockItem> bblocks;  // backward k-blocks: longer, so fewer pencil partials
         size_t tbytes, pbytes;
         size_t pmat;    // backward: one k-block's pencil partials (bytes)
-        size_t xbytes;  // backward, one-wavefront classes: the per-k adjoint matrices
+        size_t xbytes;  // backward: the per-k adjoint matrices
         int cls;
     };
     std::vector<PB> all;
@@ -283,7 +286,7 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
                     pb.bblocks.push_back(bi);
                 }
                 pb.pbytes = mat_bytes * pb.bblocks.size();
-                pb.xbytes = kClasses[cls].wave ? (size_t)3 * nn * 16 * (size_t)(a1 - a0) : 0;
+                pb.xbytes = (size_t)3 * nn * 16 * (size_t)(a1 - a0);
                 all.push_back(std::move(pb));
             }
         }
@@ -304,6 +307,17 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
         std::vector<std::vector<BlockItem>> cls_blocks(kNumClasses);
         auto flush = [&]() {
             if (cur.pencil_count == 0) return;
+            // pencil groups: runs of one model, at most kPencilGroup long
+            cur.pgroup_begin = (int)cs.pgroups.size();
+            for (int p = cur.pencil_begin; p < cur.pencil_begin + cur.pencil_count;) {
+                int q = p + 1;
+                while (q < cur.pencil_begin + cur.pencil_count && q - p < kPencilGroup &&
+                       cs.pencils[q].model == cs.pencils[p].model)
+                    ++q;
+                cs.pgroups.push_back(PencilGroup{p, q - p});
+                p = q;
+            }
+            cur.pgroup_count = (int)cs.pgroups.size() - cur.pgroup_begin;
             cur.grange_begin = (int)cs.granges.size();
             if (!with_p) {
                 // forward: deal whole pencils round-robin into eight bins, one per XCD
@@ -364,10 +378,9 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
                 b.xbuf_off = -1;
                 if (with_p) {
                     poff += mat;
-                    if (kClasses[pb.cls].wave) {
-                        b.xbuf_off = xoff;
-                        xoff += 3 * nn * b.count;
-                    }
+                    b.xbuf_off = xoff;
+                    b.xfull = kClasses[pb.cls].wave ? 0 : 1;
+                    xoff += 3 * nn * b.count;
                 }
                 cls_blocks[pb.cls].push_back(b);
             }
@@ -393,6 +406,7 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
     append_blob(P->blob, P->tab_off[9], P->grp_rho);
     for (kubo_plan_s::ChunkSet* cs : {&P->fwd, &P->bwd}) {
         append_blob(P->blob, cs->tab_pencils, cs->pencils);
+        append_blob(P->blob, cs->tab_pgroups, cs->pgroups);
         append_blob(P->blob, cs->tab_blocks, cs->blocks);
         append_blob(P->blob, cs->tab_granges, cs->granges);
     }
@@ -561,7 +575,7 @@ kubo_status enqueue_forward(kubo_plan_s* P, const double* t, const double* ef, d
     HIP_TRY(launch_clear(status, s));
     HIP_TRY(launch_hermproj(tb, P->n_models, P->t_elems, t, tp, s));
     for (const Chunk& c : P->fwd.chunks) {
-        HIP_TRY(launch_pencil(tb, c.pencil_begin, c.pencil_count, tp, tbuf, tensor, s));
+        HIP_TRY(launch_pencil(tb, c.pgroup_begin, c.pgroup_count, P->max_nn, tp, tbuf, tensor, s));
         for (int k = 0; k < kNumClasses; ++k) {
             if (c.cls[k].count == 0) continue;
             TimedScope ts(P, s, tensor ? 2 : 0, c.cls_kpts[k]);
@@ -627,7 +641,7 @@ kubo_status enqueue_backward(kubo_plan_s* P, const double* t, const double* ef, 
     HIP_TRY(launch_hermproj(tb, P->n_models, P->t_elems, t, tp, s));
     HIP_TRY(launch_zero(grad, 2 * P->t_elems, s));
     for (const Chunk& c : P->bwd.chunks) {
-        HIP_TRY(launch_pencil(tb, c.pencil_begin, c.pencil_count, tp, tbuf, false, s));
+        HIP_TRY(launch_pencil(tb, c.pgroup_begin, c.pgroup_count, P->max_nn, tp, tbuf, false, s));
         for (int k = 0; k < kNumClasses; ++k) {
             if (c.cls[k].count == 0) continue;
             WgLaunch L{};
@@ -656,8 +670,7 @@ kubo_status enqueue_backward(kubo_plan_s* P, const double* t, const double* ef, 
                 HIP_TRY(launch_adjoint_wg(L, kClasses[k].np, s));
             }
             ts.finish();
-            if (kClasses[k].wave)
-                HIP_TRY(launch_pacc(tb, c.cls[k].begin, c.cls[k].count, P->max_nn, xbuf, pbuf, status, s));
+            HIP_TRY(launch_pacc(tb, c.cls[k].begin, c.cls[k].count, P->max_nn, xbuf, pbuf, status, s));
         }
         HIP_TRY(launch_gacc(tb, tb.granges, c.grange_begin, c.grange_count, P->max_group, P->max_nn,
                             pbuf, grad, s));

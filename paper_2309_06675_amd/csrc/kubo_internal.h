@@ -40,14 +40,23 @@ struct PencilItem {
 // One k-block: count consecutive i0 of one pencil.
 struct BlockItem {
     int model, i0, count, slot;
-    int i1, i2, pad0, pad1;
+    int i1, i2;
+    int xfull;  // adjoint: 1 if its per-k matrices are stored whole, 0 if upper triangles only
+    int pad1;
     long long tbuf_off;  // its pencil's T matrices (chunk-relative)
     long long pbuf_off;  // adjoint: its pencil-sum matrices (chunk-relative)
-    long long xbuf_off;  // adjoint, one-wavefront classes: its k-points' Hbar, vbar_x,
-                         // vbar_y (chunk-relative; -1 for the workgroup class)
+    long long xbuf_off;  // adjoint: its k-points' Hbar, vbar_x, vbar_y (chunk-relative;
+                         // -1 in the forward)
 };
 
 constexpr int kMaxR0 = 16;  // distinct R_x values per model
+
+// Up to kPencilGroup consecutive pencils of one model whose partial Bloch sums one
+// workgroup forms together (each hopping read once for the group).
+constexpr int kPencilGroup = 8;
+struct PencilGroup {
+    int first, count;
+};
 
 // A run of consecutive k-blocks of one model (the adjoint's transposed Bloch sum).
 struct GaccRange {
@@ -65,6 +74,7 @@ struct Tables {
     const int* grp_rho;   // index of the R_x group of each grouped entry
     const int* negr;
     const PencilItem* pencils;
+    const PencilGroup* pgroups;
     const BlockItem* blocks;
     const GaccRange* granges;
 };

@@ -58,9 +58,10 @@ hipError_t launch_clear(unsigned* status, hipStream_t s);
 hipError_t launch_zero(double* p, long long count, hipStream_t s);
 hipError_t launch_hermproj(const Tables& tb, int n_models, long long total, const double* t,
                            double* tp, hipStream_t s);
-// with_z: also the i R_z-weighted partial sums (third set, for the Hall tensor)
-hipError_t launch_pencil(const Tables& tb, int item_begin, int item_count, const double* tp,
-                         double* tbuf, bool with_z, hipStream_t s);
+// the partial Bloch sums of the pencil groups [group_begin, group_begin + group_count);
+// with_z: also the i R_z-weighted sums (third set, for the Hall tensor)
+hipError_t launch_pencil(const Tables& tb, int group_begin, int group_count, long long max_nn,
+                         const double* tp, double* tbuf, bool with_z, hipStream_t s);
 hipError_t launch_forward_wave(const FwdLaunch& L, hipStream_t s);
 // pencil sums of the adjoint matrices of blocks [begin, begin + count):
 // PH_rho = sum_k e^{-i k0 rho}(Hbar - i rho vbar_x), PY_rho = sum_k e^{-i k0 rho} vbar_y

@@ -1222,8 +1222,9 @@ __device__ __forceinline__ void wg_phi_at(double x, const double* __restrict__ e
 }
 
 // ---------------------------------------------------------------------------
-// k_adjoint_wg: reverse mode per k-point (see the one-wavefront notes in
-// kubo_device.hip for the formulas); writes the block's pencil partials.
+// k_adjoint_wg: reverse mode per k-point (the formulas of the one-wavefront
+// adjoint in kubo_wave.hip); stores each k-point's Hbar, vbar_x, vbar_y, from
+// which k_pacc forms the block's pencil partials.
 // ---------------------------------------------------------------------------
 template <bool SMALL>
 __global__ __launch_bounds__(kWgThreads, SMALL ? 2 : 1) void k_adjoint_wg(WgLaunch a) {
@@ -1234,7 +1235,6 @@ __global__ __launch_bounds__(kWgThreads, SMALL ? 2 : 1) void k_adjoint_wg(WgLaun
     const double delta = 1e-5 * scl;
     const WgScratch X = wg_scratch(reinterpret_cast<double2*>(a.scratch), a.slot_elems, blockIdx.x);
     const double2* tbuf = reinterpret_cast<const double2*>(a.tbuf);
-    double2* pbuf = reinterpret_cast<double2*>(a.pbuf);
     for (ItemSchedule sc = xcd_schedule(a.item_count); sc.next < sc.end; sc.next += sc.step) {
         const int item = sc.next;
         const BlockItem it = a.tb.blocks[a.item_begin + item];
@@ -1243,8 +1243,6 @@ __global__ __launch_bounds__(kWgThreads, SMALL ? 2 : 1) void k_adjoint_wg(WgLaun
         const long long nn = (long long)n * n;
         const double2* T0 = tbuf + it.tbuf_off;
         const double2* T1 = T0 + (long long)md.nR0 * nn;
-        double2* PH = pbuf + it.pbuf_off;
-        double2* PY = PH + (long long)md.nR0 * nn;
         const int* r0 = a.tb.r0val + md.r0_first;
         const double* ef = a.e_fermi + md.f_off;
         const double* sb = a.sbar + md.f_off;
@@ -1351,22 +1349,17 @@ __global__ __launch_bounds__(kWgThreads, SMALL ? 2 : 1) void k_adjoint_wg(WgLaun
                     [=](int k, int j) { return c_conj(U[j * n + k]); });
             wg_gemm<false, false>(S, VX, n, [=](int i, int k) { return U[i * n + k]; },
                     [=](int k, int j) { return P[k * n + j]; });
-            for (long long e = threadIdx.x; e < (long long)md.nR0 * nn; e += kWgThreads) {
-                const int rho = (int)(e / nn);
-                const long long ij = e - (long long)rho * nn;
-                const double2 pc = c_conj(S.ph[rho]);
-                const double2 w = c_sub(W[ij], c_scale((double)r0[rho], c_i(VY[ij])));
-                const double2 h1 = c_mul(pc, w);
-                const double2 y1 = c_mul(pc, VX[ij]);
-                if (!isfinite(h1.x + h1.y + y1.x + y1.y)) atomicOr(a.status, kStatNonFinite);
-                if (kk == 0) {
-                    PH[e] = h1;
-                    PY[e] = y1;
-                } else {
-                    PH[e] = c_add(PH[e], h1);
-                    PY[e] = c_add(PY[e], y1);
-                }
+            // the k-point's Hbar, vbar_x, vbar_y, whole, for the block's pencil sums (k_pacc)
+            double2* Xk = reinterpret_cast<double2*>(a.xbuf) + it.xbuf_off + (long long)kk * 3 * nn;
+            bool bad = false;
+            for (int e = threadIdx.x; e < n * n; e += kWgThreads) {
+                const double2 h = W[e], x = VY[e], y = VX[e];
+                bad |= !isfinite(h.x + h.y + x.x + x.y + y.x + y.y);
+                Xk[e] = h;
+                Xk[nn + e] = x;
+                Xk[2 * nn + e] = y;
             }
+            if (bad) atomicOr(a.status, kStatNonFinite);
             __syncthreads();
         }
     }
