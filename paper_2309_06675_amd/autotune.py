@@ -1,12 +1,16 @@
 """Autotuner for the per-orbital-count launch shape (kubo_tile).
 
-For each orbital count n it times the per-k kernel on a sample of k-points of a
-representative model and keeps the fastest of:
+For each orbital count n it times the per-k kernel on a representative model
+and keeps the fastest of:
   * threads: 64 (one wavefront per k-point, n <= 32 only) or 256 (one workgroup),
   * k_block: the number of consecutive k-points of a pencil one work item holds.
-Timing uses the library's own event records (KUBO_F_TIMING) around the per-k
-kernel launches.  Results go to a JSON cache keyed by device name and n, which
-Plan consults when no tiles are given.
+The sample is a plan of several copies of the model on its full grid (eight
+32^3 grids by default, as in a batched plan), so every candidate launches many
+times more work items than the GPU holds at once and the timing is the steady
+state rather than how well a small sample fills the GPU.  Timing uses the
+library's own event records (KUBO_F_TIMING) around the per-k kernel launches.
+Results go to a JSON cache keyed by device name and n, which Plan consults when
+no tiles are given.
 
     python -m paper_2309_06675_amd.autotune --ns 8,12,16,...,64 --n-R 125 --nf 16
 """
@@ -18,8 +22,6 @@ import json
 import os
 import time
 from typing import Dict, Iterable, List, Optional, Tuple
-
-import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuned_tiles.json")
@@ -58,7 +60,7 @@ def lookup(ns: Iterable[int], path: str = CACHE, device: Optional[str] = None) -
 
 
 def tune_one(n: int, L: int = 2, lam: float = 1.0, grid=(32, 32, 32), nf: int = 16,
-             eta: float = 1e-3, kT: float = 0.0, sample_pencils: int = 256,
+             eta: float = 1e-3, kT: float = 0.0, copies: int = 8,
              k_blocks=(8, 16, 32), reps: int = 3, seed: int = 777) -> Dict:
     """Time every candidate shape for orbital count n; returns the best and all timings."""
     import torch
@@ -66,16 +68,18 @@ def tune_one(n: int, L: int = 2, lam: float = 1.0, grid=(32, 32, 32), nf: int = 
     from . import kubo, synth
 
     m = synth.random_model(n, L, lam, seed + n)
-    count = min(sample_pencils * grid[0], int(np.prod(grid)))
-    t = kubo.to_device_t([m])
+    models = [m] * copies
+    t = kubo.to_device_t(models)
     ef = torch.linspace(-3.0, 3.0, nf, dtype=torch.float64, device="cuda").reshape(1, nf)
+    ef = ef.repeat(copies, 1).contiguous()
     threads = (64, 256) if n <= 32 else (256,)
     results = []
     for th in threads:
         for kb in k_blocks:
             kb = min(kb, grid[0])
-            plan = kubo.Plan([m], grid=grid, n_fermi=nf, flags=kubo.KUBO_F_TIMING,
-                             tiles=[(n, th, kb)], slabs=[(0, count)])
+            plan = kubo.Plan(models, grid=grid, n_fermi=nf,
+                             flags=kubo.KUBO_F_TIMING | kubo.KUBO_F_FORWARD_ONLY,
+                             tiles=[(n, th, kb)])
             plan.forward(t, ef, eta, kT)  # warm-up (also uploads the tables)
             torch.cuda.synchronize()
             plan.kernel_time(0, reset=True)
@@ -83,7 +87,8 @@ def tune_one(n: int, L: int = 2, lam: float = 1.0, grid=(32, 32, 32), nf: int = 
                 plan.forward(t, ef, eta, kT)
             ms, launches, kpts = plan.kernel_time(0)
             results.append({"threads": th, "k_block": kb, "ms": ms / reps,
-                            "k_points_per_s": kpts / (ms / 1e3)})
+                            "k_points_per_s": kpts / (ms / 1e3), "items_k_points": kpts // reps})
+            del plan
     best = min(results, key=lambda r: r["ms"])
     return {"threads": best["threads"], "k_block": best["k_block"],
             "k_points_per_s": best["k_points_per_s"], "candidates": results}
