@@ -45,8 +45,9 @@ struct WgLds {
     double red[2 * (kWgThreads / 64)];
     int flag;
     // dead during the reduction from lam on: the n <= 64 kernels put the
-    // matrix there (over the end of the struct, into their dynamic extension)
-    double lam[kWgMaxN];
+    // matrix there (over the end of the struct, into their dynamic extension);
+    // 16-byte aligned so that its complex elements are aligned
+    alignas(16) double lam[kWgMaxN];
     double cs[2 * kWgMaxN];
     double en[kWgMaxN];
     double dn[kWgMaxN];
@@ -71,6 +72,7 @@ constexpr size_t kWgBigLds = 160 * 1024;
 constexpr int kWgSmallN = 64;
 constexpr size_t kWgSmallPart = sizeof(double2) * (kWgThreads / 64) * kWgSmallN;
 static_assert(sizeof(WgLds) <= kWgSmallLds, "LDS layout");
+static_assert(offsetof(WgLds, lam) % 16 == 0 && offsetof(WgLds, ta) % 16 == 0, "LDS alignment");
 static_assert(offsetof(WgLds, ta) + sizeof(double2) * kWgMaxN * (kWgMaxN + 1) / 2 <= kWgBigLds,
               "packed matrix in the LDS scratch region");
 // the scratch region: from ta to the end of the dynamic allocation
@@ -132,6 +134,14 @@ __device__ __forceinline__ double wg_wave_reduce(double v, Op op) {
         v = op(join(lo[0], hi[0]), join(lo[1], hi[1]));
     }
     return v;
+}
+
+// value of a per-lane register held by lane src of the wavefront (src wave-uniform)
+__device__ __forceinline__ double wg_lane_read(double v, int src) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), src);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), src);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
 // Workgroup sum of one double (all threads get the result).
@@ -382,23 +392,15 @@ __device__ void wg_tridiag_packed(WgLds& S, double2* __restrict__ P, int n, doub
 }
 
 // ---------------------------------------------------------------------------
-// step 2a for n <= 64, the same reduction restructured (measured faster there;
-// wg_tridiag stays faster at n = 128), run on an LDS copy of the matrix.  Per
-// step: column k through LDS; p = A22 v in column form (A22 is Hermitian,
-// p_r = sum_c conj(A_cr) v_c), each wavefront summing every fourth c with
-// lanes over r, the four partial sums combined through an LDS buffer (part);
-// the rank-2 update with wavefronts over rows and lanes over columns.  Six
-// barriers per step.
+// step 2a for n <= 64, the same reduction on an LDS copy of the whole matrix.
+// Per step: the reflector from column k (held in S.xv with its norm partials);
+// p = A22 v in column form (A22 is Hermitian, p_r = sum_c conj(A_cr) v_c), each
+// wavefront summing every fourth c with lanes over r into an LDS buffer (part),
+// together with its share of v^+ p; the rank-2 update with wavefronts over rows
+// and lanes over columns, w formed where it is needed from the partial sums of
+// p, and the lane holding column k + 1 keeping that column and its norm
+// partials for the next step.  Three barriers per step.
 // ---------------------------------------------------------------------------
-// workgroup sum with one barrier; red[base .. base+3] must not be reused
-// before the next barrier
-__device__ __forceinline__ double wg_sum1(double v, double* red, int base) {
-    v = wg_wave_reduce(v, [](double x, double y) { return x + y; });
-    if ((threadIdx.x & 63) == 0) red[base + (threadIdx.x >> 6)] = v;
-    __syncthreads();
-    return (red[base] + red[base + 1]) + (red[base + 2] + red[base + 3]);
-}
-
 __device__ void wg_tridiag_cols(WgLds& S, double2* __restrict__ P, int n, double2* __restrict__ part) {
     // part: [NW][kWgSmallN] partial sums of p (n <= kWgSmallN)
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -407,14 +409,22 @@ __device__ void wg_tridiag_cols(WgLds& S, double2* __restrict__ P, int n, double
         const double r = __builtin_amdgcn_rcp(x);
         return fma(r, fma(-x, r, 1.0), r);
     };
-    for (int k = 0; k < n - 1; ++k) {
+    auto wave_sum = [](double v) { return wg_wave_reduce(v, [](double x, double y) { return x + y; }); };
+    // column 0 and the partial sums of its squared norm below the subdiagonal (S.red[0..NW))
+    {
         double nrm_part = 0.0;
-        for (int r = k + 1 + tid; r < n; r += kWgThreads) {
-            const double2 x = P[r * n + k];
+        for (int r = 1 + tid; r < n; r += kWgThreads) {
+            const double2 x = P[r * n];
             S.xv[r] = x;
-            if (r > k + 1) nrm_part = fma(x.x, x.x, fma(x.y, x.y, nrm_part));
+            if (r > 1) nrm_part = fma(x.x, x.x, fma(x.y, x.y, nrm_part));
         }
-        const double xn2 = wg_sum1(nrm_part, S.red, 0);
+        nrm_part = wave_sum(nrm_part);
+        if (lane == 0) S.red[w] = nrm_part;
+        __syncthreads();
+    }
+    for (int k = 0; k < n - 1; ++k) {
+        // S.xv holds column k (rows > k), S.red[0..NW) its norm partials
+        const double xn2 = (S.red[0] + S.red[1]) + (S.red[2] + S.red[3]);
         const double2 alpha = S.xv[k + 1];
         double beta;
         double2 tau, scal;
@@ -442,8 +452,23 @@ __device__ void wg_tridiag_cols(WgLds& S, double2* __restrict__ P, int n, double
             P[r * n + k] = v;
         }
         __syncthreads();
-        if (tau.x == 0.0 && tau.y == 0.0) continue;
-        // partial p_r over c = k + 1 + w (mod NW), two interleaved accumulators
+        if (tau.x == 0.0 && tau.y == 0.0) {
+            // nothing to reflect: the next column as it stands
+            double nrm_part = 0.0;
+            for (int r = k + 2 + tid; r < n; r += kWgThreads) {
+                const double2 x = P[r * n + k + 1];
+                S.xv[r] = x;
+                if (r > k + 2) nrm_part = fma(x.x, x.x, fma(x.y, x.y, nrm_part));
+            }
+            nrm_part = wave_sum(nrm_part);
+            __syncthreads();
+            if (lane == 0) S.red[w] = nrm_part;
+            __syncthreads();
+            continue;
+        }
+        // partial p_r over c = k + 1 + w (mod NW), two interleaved accumulators, and this
+        // wavefront's share of mu = v^+ p (real) into S.red[NW + w]
+        double mpart = 0.0;
         for (int r = k + 1 + lane; r < n; r += 64) {
             double2 a0 = c_make(0.0, 0.0), a1 = a0;
             int c = k + 1 + w;
@@ -452,27 +477,44 @@ __device__ void wg_tridiag_cols(WgLds& S, double2* __restrict__ P, int n, double
                 a1 = c_fmac(P[(c + NW) * n + r], S.vv[c + NW], a1);
             }
             if (c < n) a0 = c_fmac(P[c * n + r], S.vv[c], a0);
-            part[w * kWgSmallN + r] = c_add(a0, a1);
+            const double2 pw = c_add(a0, a1);
+            part[w * kWgSmallN + r] = pw;
+            const double2 vr = S.vv[r];
+            mpart = fma(vr.x, pw.x, fma(vr.y, pw.y, mpart));
         }
+        mpart = wave_sum(mpart);
+        if (lane == 0) S.red[NW + w] = mpart;
         __syncthreads();
-        double2 p = c_make(0.0, 0.0), v = p;
-        double mpart = 0.0;
-        const int r = k + 1 + tid;
-        if (r < n) {
-            p = c_add(c_add(part[r], part[kWgSmallN + r]), c_add(part[2 * kWgSmallN + r], part[3 * kWgSmallN + r]));
-            v = S.vv[r];
-            mpart = v.x * p.x + v.y * p.y;
-        }
-        const double mu = wg_sum1(mpart, S.red, NW);  // v^+ p (real)
+        const double mu = (S.red[NW] + S.red[NW + 1]) + (S.red[NW + 2] + S.red[NW + 3]);
         const double t2 = 0.5 * (tau.x * tau.x + tau.y * tau.y) * mu;
-        if (r < n) S.wv[r] = c_sub(c_mul(tau, p), c_scale(t2, v));
-        __syncthreads();
-        // A22 <- A22 - v w^+ - w v^+: wavefronts over rows, lanes over columns
+        // w_r = tau p_r - t2 v_r, formed where it is needed from the four partial sums of p
+        auto w_of = [&](int r) {
+            const double2 pr = c_add(c_add(part[r], part[kWgSmallN + r]),
+                                     c_add(part[2 * kWgSmallN + r], part[3 * kWgSmallN + r]));
+            return c_sub(c_mul(tau, pr), c_scale(t2, S.vv[r]));
+        };
+        // A22 <- A22 - v w^+ - w v^+: wavefronts over rows, lanes over columns; the lane
+        // holding column k + 1 keeps the updated column for the next step and the partial
+        // sums of its squared norm below the next subdiagonal
+        const int c = k + 1 + lane;  // n <= 64: one column per lane
+        const double2 wc = (c < n) ? w_of(c) : c_make(0.0, 0.0);
+        const double2 vc = (c < n) ? S.vv[c] : c_make(0.0, 0.0);
+        double nrm_part = 0.0;
         for (int rr = k + 1 + w; rr < n; rr += NW) {
-            const double2 vr = S.vv[rr], wr = S.wv[rr];
-            for (int c = k + 1 + lane; c < n; c += 64)
-                P[rr * n + c] = c_rank2c(P[rr * n + c], vr, S.wv[c], wr, S.vv[c]);
+            // v_rr and w_rr from the lane that holds column rr (rr is wave-uniform)
+            const int src = rr - k - 1;
+            const double2 vr = c_make(wg_lane_read(vc.x, src), wg_lane_read(vc.y, src));
+            const double2 wr = c_make(wg_lane_read(wc.x, src), wg_lane_read(wc.y, src));
+            if (c < n) {
+                const double2 x = c_rank2c(P[rr * n + c], vr, wc, wr, vc);
+                P[rr * n + c] = x;
+                if (lane == 0 && rr > k + 1) {
+                    S.xv[rr] = x;
+                    if (rr > k + 2) nrm_part = fma(x.x, x.x, fma(x.y, x.y, nrm_part));
+                }
+            }
         }
+        if (lane == 0) S.red[w] = nrm_part;
         __syncthreads();
     }
     if (tid == 0) {
@@ -626,9 +668,12 @@ __device__ void wg_bisect(WgLds& S, int n, double& pivmin_out, double& span_out)
 // ---------------------------------------------------------------------------
 __device__ void wg_twisted(WgLds& S, const WgScratch& X, int n, double pivmin, double* __restrict__ R,
                            size_t r_doubles) {
-    // the pivots of G eigenvectors at a time in the LDS region R: dp[i][t] at R[i G + t],
-    // dm[i][t] at R[(n + i) G + t] (consecutive threads, consecutive words)
-    const int Gmax = (int)(r_doubles / (2 * (size_t)n));
+    // one pivot array per eigenvector in the LDS region R, G eigenvectors at a time
+    // (piv[i][t] at R[i G + t]: consecutive threads, consecutive words).  Pass 1 stores
+    // the forward pivots dp_i; pass 2 runs the backward pivots dm_i without storing them
+    // and picks the twist index r; pass 3 recomputes dm_i for i > r into the slots of
+    // dp_i, which the solve above r no longer needs.
+    const int Gmax = (int)(r_doubles / (size_t)n);
     const int G = Gmax < n ? Gmax : n;
     // reciprocal: hardware estimate and one Newton step (|q| >= pivmin keeps it finite)
     auto rcp = [](double q) {
@@ -639,13 +684,12 @@ __device__ void wg_twisted(WgLds& S, const WgScratch& X, int n, double pivmin, d
         const int t = threadIdx.x, j = g0 + t;
         if (t < G && j < n) {
             const double lam = S.lam[j];
-            double* dp = R + t;
-            double* dm = R + (size_t)n * G + t;
+            double* piv = R + t;
             double qv = 1.0, e2prev = 0.0;
             for (int i = 0; i < n; ++i) {
                 double qi = (S.d[i] - lam) - e2prev * rcp(qv);
                 if (fabs(qi) < pivmin) qi = -pivmin;
-                dp[i * G] = qi;
+                piv[i * G] = qi;
                 qv = qi;
                 e2prev = S.e[i] * S.e[i];
             }
@@ -655,31 +699,37 @@ __device__ void wg_twisted(WgLds& S, const WgScratch& X, int n, double pivmin, d
             for (int i = n - 1; i >= 0; --i) {
                 double qi = (S.d[i] - lam) - ((i < n - 1) ? S.e[i] * S.e[i] * rcp(qv) : 0.0);
                 if (fabs(qi) < pivmin) qi = -pivmin;
-                dm[i * G] = qi;
                 qv = qi;
-                const double g = dp[i * G] + qi - (S.d[i] - lam);
+                const double g = piv[i * G] + qi - (S.d[i] - lam);
                 if (fabs(g) < best) {
                     best = fabs(g);
                     gam = g;
                     r = i;
                 }
             }
+            qv = 1.0;
+            for (int i = n - 1; i > r; --i) {
+                double qi = (S.d[i] - lam) - ((i < n - 1) ? S.e[i] * S.e[i] * rcp(qv) : 0.0);
+                if (fabs(qi) < pivmin) qi = -pivmin;
+                piv[i * G] = qi;
+                qv = qi;
+            }
             double nrm = 1.0;
             double z = 1.0;
             for (int i = r - 1; i >= 0; --i) {
-                z = -(S.e[i] * rcp(dp[i * G])) * z;
-                dp[i * G] = z;  // the pivot is spent: keep z_i in its place
+                z = -(S.e[i] * rcp(piv[i * G])) * z;
+                piv[i * G] = z;  // the pivot is spent: keep z_i in its place
                 nrm += z * z;
             }
             z = 1.0;
             for (int i = r + 1; i < n; ++i) {
-                z = -(S.e[i - 1] * rcp(dm[i * G])) * z;
-                dm[i * G] = z;
+                z = -(S.e[i - 1] * rcp(piv[i * G])) * z;
+                piv[i * G] = z;
                 nrm += z * z;
             }
             const double inv = 1.0 / sqrt(nrm);
             for (int i = 0; i < n; ++i) {
-                const double zi = (i < r) ? dp[i * G] : ((i == r) ? 1.0 : dm[i * G]);
+                const double zi = (i == r) ? 1.0 : piv[i * G];
                 X.U[(long long)i * n + j] = c_make(zi * inv, 0.0);
             }
             // (T - lam) z = gam e_r with z_r = 1: Rayleigh-quotient correction
