@@ -50,9 +50,9 @@ __device__ __forceinline__ double2 unit_phase(long long m, long long N) {
     m %= N;
     if (m < 0) m += N;
     if (2 * m > N) m -= N;
-    double s, c;
-    sincospi(2.0 * (double)m / (double)N, &s, &c);
-    return c_make(c, s);
+    // separate sine and cosine: sincospi returns its cosine through private memory
+    const double x = 2.0 * (double)m / (double)N;
+    return c_make(cospi(x), sinpi(x));
 }
 
 // e^{i (2 pi a1/N1 + 2 pi a2/N2)} with exact rational reduction of the angle.

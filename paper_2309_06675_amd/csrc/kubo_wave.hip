@@ -679,7 +679,8 @@ __device__ void wave_stage_velocity(WaveLds<NP>& S, int n, int nR0, const double
     constexpr int LD = WaveLds<NP>::LD;
     constexpr int NU = NP * (NP + 1) / 2;
     constexpr int PER = (NU + 63) / 64;
-    const int lane = threadIdx.x & 63;
+    int lane = threadIdx.x & 63;
+    asm volatile("" : "+v"(lane));  // recomputed here, not hoisted out of the k loop
     const long long nn = (long long)n * n;
     double2 acc[PER];
     int off[PER];  // -1: padding
@@ -921,7 +922,8 @@ template <int NP>
 __device__ bool wave_eigen(WaveLds<NP>& S, const ModelDev& md, const double2* __restrict__ T0,
                            const int* __restrict__ r0, int i0, int max_iter, bool& vx_in_p) {
     constexpr int LD = WaveLds<NP>::LD;
-    const int lane = threadIdx.x & 63;
+    int lane = threadIdx.x & 63;
+    asm volatile("" : "+v"(lane));  // recomputed here, not hoisted out of the k loop
     const int n = md.n;
     const long long nn = (long long)n * n;
     if (lane < md.nR0) S.ph[lane] = unit_phase((long long)i0 * r0[lane], md.N0);
