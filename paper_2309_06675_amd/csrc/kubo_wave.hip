@@ -1370,6 +1370,10 @@ __global__ __launch_bounds__(64) void k_adjoint_wave(WgLaunch a) {
         const double* sb = a.sbar + md.f_off;
         const double invN = 1.0 / (double)md.Nk;
         for (int kk = 0; kk < it.count; ++kk) {
+            // lane-derived values recomputed per k-point rather than hoisted out of the loop
+            int lane_k = threadIdx.x & 63;
+            asm volatile("" : "+v"(lane_k));
+            const int lane = lane_k, g = lane_k >> 4, c16 = lane_k & 15;
             // ---- recompute: E, U, A = U^+ v_x U, B = U^+ v_y U
             bool vx_in_p;
             const bool ok = wave_eigen<NP>(S, md, T0, r0, it.i0 + kk, max_iter, vx_in_p);
