@@ -882,7 +882,11 @@ void kubo_plan_destroy(kubo_plan_t plan) {
 }
 
 const char* kubo_status_string(kubo_status status) {
-    switch (status) {
+    // a C caller may pass any int: read the value without loading an enum that C++
+    // would consider out of range
+    int32_t code = 0;
+    std::memcpy(&code, &status, sizeof(code));
+    switch (code) {
         case KUBO_OK:
             return "KUBO_OK";
         case KUBO_E_INVALID:
