@@ -108,8 +108,8 @@ typedef struct {
  *                   or forward only with KUBO_F_FORWARD_ONLY)
  * The k-grid is processed in chunks of kx pencils whose partial Bloch sums fit
  * a buffer of KUBO_CHUNK_MB megabytes (environment variable read here; default
- * 512); the backward's per-k-block pencil partials and per-k adjoint
- * matrices get sixteen times that.
+ * 2048); the backward's per-k-block pencil partials and per-k adjoint
+ * matrices get four times that.
  * Larger chunks mean fewer launches and a larger workspace.
  * Errors: KUBO_E_INVALID for NULL pointers, n_orb < 1, n_R < 1, grid < 1,
  * duplicate R, an R whose negative is missing, a slab outside the grid or a

@@ -106,19 +106,28 @@ __device__ __forceinline__ double2 c_rank2c(double2 acc, double2 a, double2 b, d
     return acc;
 }
 
-// Work-item schedule of the persistent per-k kernels.  Workgroups are handed to
-// the eight XCDs round-robin (workgroup b runs on XCD b % 8), so each XCD gets a
-// contiguous share of the item list: the k-blocks of one pencil, which read the
-// same partial Bloch sums, then run inside one XCD and share its L2.
-struct ItemSchedule {
-    int next, end, step;
-};
-__device__ __forceinline__ ItemSchedule xcd_schedule(int count) {
-    const int G = (int)gridDim.x;
-    if (G < 8 || (G & 7) != 0) return ItemSchedule{(int)blockIdx.x, count, G};
-    const int x = (int)blockIdx.x & 7, j = (int)blockIdx.x >> 3;
-    const int b = (int)((long long)count * x / 8), e = (int)((long long)count * (x + 1) / 8);
-    return ItemSchedule{b + j, e, G >> 3};
+// Work queue of the persistent per-k kernels.  A launch's work units are split
+// into eight equal bins, one per XCD: workgroups are handed to the XCDs
+// round-robin (workgroup b runs on XCD b % 8), so the consecutive units of a bin
+// (the k-blocks of one pencil, which read the same partial Bloch sums) run inside
+// one XCD and share its L2.  A workgroup takes the next unit of its own bin with
+// an atomic counter (ctr[0..7], zero at the start of the launch) and, once that
+// bin is empty, the next units of the other bins in turn, so units of uneven cost
+// balance over the whole GPU and no XCD idles while another has work.  Returns -1
+// when every bin is empty (then every later call returns -1 too).  Called by one
+// lane; `probe` is that lane's state (0 before the first call).
+__device__ __forceinline__ int queue_take(unsigned* ctr, int count, int& probe) {
+    const int x = (int)blockIdx.x & 7;
+    while (probe < 8) {
+        const int b = (x + probe) & 7;
+        const int lo = (int)((long long)count * b / 8), hi = (int)((long long)count * (b + 1) / 8);
+        if (lo < hi) {
+            const unsigned i = atomicAdd(ctr + b, 1u);
+            if (i < (unsigned)(hi - lo)) return lo + (int)i;
+        }
+        ++probe;
+    }
+    return -1;
 }
 
 }  // namespace kubo

@@ -34,8 +34,9 @@ namespace kubo {
 // ---------------------------------------------------------------------------
 // k_clear: zero the status word (a kernel, not a memset, so graphs replay it)
 // ---------------------------------------------------------------------------
-__global__ void k_clear_status(unsigned* status) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) status[0] = 0u;
+__global__ void k_clear_status(unsigned* status, unsigned* queues, int n_queue_words) {
+    if (threadIdx.x == 0) status[0] = 0u;
+    for (int i = threadIdx.x; i < n_queue_words; i += blockDim.x) queues[i] = 0u;
 }
 
 __global__ void k_zero(double* p, long long count) {
@@ -294,8 +295,8 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(Tables tb, int nF, in
 // ---------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_clear(unsigned* status, hipStream_t s) {
-    hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, s, status);
+hipError_t launch_clear(unsigned* status, unsigned* queues, int n_queue_words, hipStream_t s) {
+    hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(256), 0, s, status, queues, n_queue_words);
     return hipGetLastError();
 }
 

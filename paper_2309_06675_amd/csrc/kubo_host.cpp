@@ -22,6 +22,8 @@ using namespace kubo;
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr int kCUs = 256;   // compute units of the MI355X
+constexpr int kUnitK = 8;   // k-points per backward work unit
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // Size classes of the per-k kernels (forward and adjoint alike): one wavefront
@@ -43,6 +45,7 @@ int class_of(int n) {
 
 struct ClassRange {
     int begin = 0, count = 0;
+    int max_k = 0;  // most k-points of one item
 };
 
 struct Chunk {
@@ -73,7 +76,7 @@ struct CachedGraph {
 
 size_t chunk_cap_bytes() {
     const char* e = std::getenv("KUBO_CHUNK_MB");
-    long mb = e ? std::atol(e) : 512;
+    long mb = e ? std::atol(e) : 2048;
     if (mb < 1) mb = 1;
     return (size_t)mb << 20;
 }
@@ -103,11 +106,12 @@ struct kubo_plan_s {
     int n_orb_total = 0;    // orbitals summed over the models (length of a spin array)
     long long t_elems = 0;  // complex elements of t (all models)
     // workspace layout
-    size_t off_tables = 0, off_tp = 0, off_tbuf = 0, off_pbuf = 0, off_xbuf = 0, off_partial = 0,
+    size_t off_queues = 0, off_tables = 0, off_tp = 0, off_tbuf = 0, off_pbuf = 0, off_xbuf = 0, off_partial = 0,
            total = 0;
     size_t off_scratch = 0;
     long long slot_elems = 0;
     int wg_groups = 512;
+    int n_queues = 0;  // per-k kernel launches (forward chunks, then backward), 8 counters each
     std::vector<unsigned char> blob;
     size_t tab_off[10] = {0};
     unsigned long long id = 0;           // unique per plan (never reused)
@@ -232,7 +236,10 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
         const long long kb = d.k_begin;
         const long long kc = d.k_count < 0 ? md.Nk - kb : d.k_count;
         const long long ke = kb + kc;
-        int kblock = std::min(d.grid[0], 32);
+        // default k-block: 32 points for the one-wavefront classes, 8 for the
+        // workgroup classes (a k-point costs milliseconds there, so smaller items
+        // keep the end of a launch short)
+        int kblock = std::min(d.grid[0], d.n_orb > 32 ? 8 : 32);
         auto ti = tile_of.find(d.n_orb);
         if (ti != tile_of.end()) kblock = std::min(d.grid[0], ti->second.k_block);
         // the backward writes one set of pencil partials per k-block and sums them
@@ -340,6 +347,7 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
                 cur.cls_kpts[c] = 0;
                 for (auto& b : cls_blocks[c]) {
                     const int bi = (int)cs.blocks.size();
+                    cur.cls[c].max_k = std::max(cur.cls[c].max_k, b.count);
                     if (cs.granges.size() > (size_t)cur.grange_begin &&
                         cs.granges.back().model == b.model &&
                         cs.granges.back().begin + cs.granges.back().count == bi)
@@ -364,7 +372,7 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
             PB pb = pb0;
             if (cur.pencil_count > 0 &&
                 (cur.tbytes + pb.tbytes > cap ||
-                 (with_p && cur.pbytes + cur.xbytes + pb.pbytes + pb.xbytes > 16 * cap)))
+                 (with_p && cur.pbytes + cur.xbytes + pb.pbytes + pb.xbytes > 4 * cap)))
                 flush();
             PencilItem pi = pb.pi;
             pi.tbuf_off = (long long)(cur.tbytes / 16);
@@ -414,6 +422,9 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
     const size_t max_p = P->bwd.max_p;
 
     size_t off = kAlign;  // status word
+    P->n_queues = (int)(P->fwd.chunks.size() + P->bwd.chunks.size()) * kNumClasses;
+    P->off_queues = off;
+    off = align_up(off + (size_t)P->n_queues * 8 * sizeof(unsigned));
     P->off_tables = off;
     off = align_up(off + P->blob.size());
     P->off_tp = off;
@@ -431,10 +442,16 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
         int nmax = 1;
         for (const auto& md : P->models) nmax = std::max(nmax, md.n);
         P->slot_elems = wg_slot_elems(nmax);
+        // most work units of one launch (a backward item splits into units of
+        // at most kUnitK k-points)
         int most = 1;
-        for (const kubo_plan_s::ChunkSet* cs : {&P->fwd, &P->bwd})
-            for (const Chunk& c : cs->chunks)
-                for (int k = 0; k < kNumClasses; ++k) most = std::max(most, c.cls[k].count);
+        for (const Chunk& c : P->fwd.chunks)
+            for (int k = 0; k < kNumClasses; ++k) most = std::max(most, c.cls[k].count);
+        for (const Chunk& c : P->bwd.chunks)
+            for (int k = 0; k < kNumClasses; ++k) {
+                const int uk = std::max(1, std::min(c.cls[k].max_k, kUnitK));
+                most = std::max(most, c.cls[k].count * ((c.cls[k].max_k + uk - 1) / uk));
+            }
         P->wg_groups = std::min(P->wg_groups, most);
         if (P->wg_groups >= 8) P->wg_groups &= ~7;  // whole XCD rounds
         // only the workgroup classes use the per-workgroup scratch
@@ -562,6 +579,14 @@ struct TimedScope {
     }
 };
 
+// Grid of a workgroup-class launch: no more workgroups than the GPU holds at once
+// (one per CU for n <= 128, which takes all 160 KB of LDS; two for n <= 64), since
+// the work queue balances the items over the resident ones.
+int wg_grid_cap(const kubo_plan_s* P, int k) {
+    const int resident = kClasses[k].np > 64 ? kCUs : 2 * kCUs;
+    return std::min(P->wg_groups, resident);
+}
+
 kubo_status enqueue_forward(kubo_plan_s* P, const double* t, const double* ef, double eta,
                             double kT, double* sigma, unsigned char* ws, hipStream_t s,
                             bool tensor = false, const double* spin = nullptr) {
@@ -572,9 +597,11 @@ kubo_status enqueue_forward(kubo_plan_s* P, const double* t, const double* ef, d
     double* partial = reinterpret_cast<double*>(ws + P->off_partial);
     double* scratch = reinterpret_cast<double*>(ws + P->off_scratch);
     const int max_iter = (P->flags & KUBO_F_DEBUG_SWEEPCAP) ? 1 : kMaxSweeps;
-    HIP_TRY(launch_clear(status, s));
+    unsigned* queues = reinterpret_cast<unsigned*>(ws + P->off_queues);
+    HIP_TRY(launch_clear(status, queues, 8 * P->n_queues, s));
     HIP_TRY(launch_hermproj(tb, P->n_models, P->t_elems, t, tp, s));
-    for (const Chunk& c : P->fwd.chunks) {
+    for (size_t ci = 0; ci < P->fwd.chunks.size(); ++ci) {
+        const Chunk& c = P->fwd.chunks[ci];
         HIP_TRY(launch_pencil(tb, c.pgroup_begin, c.pgroup_count, P->max_nn, tp, tbuf, tensor, s));
         for (int k = 0; k < kNumClasses; ++k) {
             if (c.cls[k].count == 0) continue;
@@ -596,6 +623,7 @@ kubo_status enqueue_forward(kubo_plan_s* P, const double* t, const double* ef, d
                 L.max_groups = P->max_groups;
                 L.tensor = tensor ? 1 : 0;
                 L.spin = spin;
+                L.queue = queues + 8 * (ci * kNumClasses + k);
                 HIP_TRY(launch_forward_wave(L, s));
             } else {
                 WgLaunch L{};
@@ -614,9 +642,12 @@ kubo_status enqueue_forward(kubo_plan_s* P, const double* t, const double* ef, d
                 L.max_iter = max_iter;
                 L.item_begin = c.cls[k].begin;
                 L.item_count = c.cls[k].count;
-                L.max_groups = P->wg_groups;
+                L.max_groups = wg_grid_cap(P, k);
                 L.tensor = tensor ? 1 : 0;
                 L.spin = spin;
+                L.queue = queues + 8 * (ci * kNumClasses + k);
+                L.unit_k = c.cls[k].max_k;
+                L.unit_parts = 1;
                 HIP_TRY(launch_forward_wg(L, kClasses[k].np, s));
             }
             ts.finish();
@@ -637,10 +668,13 @@ kubo_status enqueue_backward(kubo_plan_s* P, const double* t, const double* ef, 
     double* xbuf = reinterpret_cast<double*>(ws + P->off_xbuf);
     double* scratch = reinterpret_cast<double*>(ws + P->off_scratch);
     const int max_iter = (P->flags & KUBO_F_DEBUG_SWEEPCAP) ? 1 : kMaxSweeps;
-    HIP_TRY(launch_clear(status, s));
+    unsigned* queues = reinterpret_cast<unsigned*>(ws + P->off_queues);
+    HIP_TRY(launch_clear(status, queues, 8 * P->n_queues, s));
     HIP_TRY(launch_hermproj(tb, P->n_models, P->t_elems, t, tp, s));
     HIP_TRY(launch_zero(grad, 2 * P->t_elems, s));
-    for (const Chunk& c : P->bwd.chunks) {
+    const size_t qbase = P->fwd.chunks.size();
+    for (size_t ci = 0; ci < P->bwd.chunks.size(); ++ci) {
+        const Chunk& c = P->bwd.chunks[ci];
         HIP_TRY(launch_pencil(tb, c.pgroup_begin, c.pgroup_count, P->max_nn, tp, tbuf, false, s));
         for (int k = 0; k < kNumClasses; ++k) {
             if (c.cls[k].count == 0) continue;
@@ -661,7 +695,12 @@ kubo_status enqueue_backward(kubo_plan_s* P, const double* t, const double* ef, 
             L.max_iter = max_iter;
             L.item_begin = c.cls[k].begin;
             L.item_count = c.cls[k].count;
-            L.max_groups = P->wg_groups;
+            L.max_groups = wg_grid_cap(P, k);
+            L.queue = queues + 8 * ((qbase + ci) * kNumClasses + k);
+            // work units of at most kUnitK k-points (a backward k-block is split),
+            // so the end of a launch waits for a few k-points, not a whole block
+            L.unit_k = std::min(c.cls[k].max_k, kUnitK);
+            L.unit_parts = (c.cls[k].max_k + L.unit_k - 1) / L.unit_k;
             TimedScope ts(P, s, 1, c.cls_kpts[k]);
             if (kClasses[k].wave) {
                 L.max_groups = P->max_groups;

@@ -25,6 +25,7 @@ struct FwdLaunch {
     // spin (per orbital, all models; NULL: no spin Hall component) weights the spin current
     int tensor;
     const double* spin;
+    unsigned* queue;  // this launch's eight work-queue counters, zero at its start
 };
 
 struct WgLaunch {
@@ -45,6 +46,10 @@ struct WgLaunch {
     int max_groups;
     int tensor;           // forward only: as FwdLaunch::tensor
     const double* spin;   // forward only: as FwdLaunch::spin
+    unsigned* queue;      // this launch's eight work-queue counters, zero at its start
+    // work unit u covers k-points [p*unit_k, (p+1)*unit_k) of item u / unit_parts,
+    // p = u % unit_parts (the forward: unit_parts = 1, one unit per item)
+    int unit_k, unit_parts;
 };
 
 long long wg_slot_elems(int nmax);
@@ -54,7 +59,9 @@ hipError_t launch_adjoint_wg(const WgLaunch& L, int np, hipStream_t s);
 // one wavefront per k-point for n <= 32 (np: the size class, 8, 16 or 32)
 hipError_t launch_adjoint_wave(const WgLaunch& L, int np, hipStream_t s);
 
-hipError_t launch_clear(unsigned* status, hipStream_t s);
+// zero the status word and n_queue_words work-queue counters (a kernel, so that it
+// is also a plain kernel node when captured into a graph)
+hipError_t launch_clear(unsigned* status, unsigned* queues, int n_queue_words, hipStream_t s);
 hipError_t launch_zero(double* p, long long count, hipStream_t s);
 hipError_t launch_hermproj(const Tables& tb, int n_models, long long total, const double* t,
                            double* tp, hipStream_t s);

@@ -1076,8 +1076,12 @@ __global__ __launch_bounds__(64) void k_forward_wave(FwdLaunch a) {
     // U's padding (rows and columns n..NP-1) is never written below: keep it finite
     for (int e = lane; e < NP * LD; e += 64) S.U[e] = c_make(0.0, 0.0);
     __syncthreads();
-    for (ItemSchedule sc = xcd_schedule(a.item_count); sc.next < sc.end; sc.next += sc.step) {
-        const int item = sc.next;
+    int probe = 0;
+    for (;;) {
+        int item = 0;
+        if (lane == 0) item = queue_take(a.queue, a.item_count, probe);
+        item = __builtin_amdgcn_readfirstlane(item);
+        if (item < 0) break;
         const BlockItem it = a.tb.blocks[a.item_begin + item];
         const ModelDev md = a.tb.models[it.model];
         const int n = md.n;
@@ -1216,6 +1220,7 @@ static hipError_t launch_forward_wave_t(const FwdLaunch& L, hipStream_t s) {
 
 hipError_t launch_forward_wave(const FwdLaunch& L, hipStream_t s) {
     if (L.item_count <= 0) return hipSuccess;
+    if (!L.queue) return hipErrorInvalidValue;
     switch (L.np) {
         case 8:
             return L.tensor ? launch_forward_wave_t<8, true>(L, s) : launch_forward_wave_t<8, false>(L, s);
@@ -1347,7 +1352,6 @@ __global__ __launch_bounds__(64) void k_adjoint_wave(WgLaunch a) {
     constexpr int NT = NP / 16;
     static_assert(NT >= 1, "the matrix-core adjoint needs NP >= 16");
     const int lane = threadIdx.x & 63;
-    const int g = lane >> 4, c16 = lane & 15;
     const double eta2 = a.eta * a.eta;
     const double scl = (a.kT > 0.0) ? fmin(a.eta, a.kT) : a.eta;
     const double delta = 1e-5 * scl;
@@ -1357,9 +1361,17 @@ __global__ __launch_bounds__(64) void k_adjoint_wave(WgLaunch a) {
     const v4d zero = {0.0, 0.0, 0.0, 0.0};
     for (int e = lane; e < NP * LD; e += 64) S.U[e] = c_make(0.0, 0.0);
     __syncthreads();
-    for (ItemSchedule sc = xcd_schedule(a.item_count); sc.next < sc.end; sc.next += sc.step) {
-        const int item = sc.next;
+    const int units = a.item_count * a.unit_parts;
+    int probe = 0;
+    for (;;) {
+        int unit = 0;
+        if (lane == 0) unit = queue_take(a.queue, units, probe);
+        unit = __builtin_amdgcn_readfirstlane(unit);
+        if (unit < 0) break;
+        const int item = unit / a.unit_parts;
+        const int kk0 = (unit - item * a.unit_parts) * a.unit_k;
         const BlockItem it = a.tb.blocks[a.item_begin + item];
+        const int kk1 = min(it.count, kk0 + a.unit_k);
         const ModelDev md = a.tb.models[it.model];
         const int n = md.n;
         const long long nn = (long long)n * n;
@@ -1369,7 +1381,7 @@ __global__ __launch_bounds__(64) void k_adjoint_wave(WgLaunch a) {
         const double* ef = a.e_fermi + md.f_off;
         const double* sb = a.sbar + md.f_off;
         const double invN = 1.0 / (double)md.Nk;
-        for (int kk = 0; kk < it.count; ++kk) {
+        for (int kk = kk0; kk < kk1; ++kk) {
             // lane-derived values recomputed per k-point rather than hoisted out of the loop
             int lane_k = threadIdx.x & 63;
             asm volatile("" : "+v"(lane_k));
@@ -1655,13 +1667,15 @@ static hipError_t launch_adjoint_wave_t(const WgLaunch& L, hipStream_t s) {
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    const int grid = L.item_count < L.max_groups ? L.item_count : L.max_groups;
+    const int units = L.item_count * L.unit_parts;
+    const int grid = units < L.max_groups ? units : L.max_groups;
     hipLaunchKernelGGL((k_adjoint_wave<NP>), dim3(grid), dim3(64), lds, s, L);
     return hipGetLastError();
 }
 
 hipError_t launch_adjoint_wave(const WgLaunch& L, int np, hipStream_t s) {
     if (L.item_count <= 0) return hipSuccess;
+    if (!L.queue || L.unit_k < 1 || L.unit_parts < 1) return hipErrorInvalidValue;
     if (np <= 16) return launch_adjoint_wave_t<16>(L, s);
     if (np <= 32) return launch_adjoint_wave_t<32>(L, s);
     return hipErrorInvalidValue;

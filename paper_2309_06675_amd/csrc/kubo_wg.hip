@@ -44,6 +44,7 @@ struct WgLds {
     double2 ph[16];
     double red[2 * (kWgThreads / 64)];
     int flag;
+    int unit[2];  // work unit taken by thread 0, double-buffered by loop parity
     // dead during the reduction from lam on: the n <= 64 kernels put the
     // matrix there (over the end of the struct, into their dynamic extension);
     // 16-byte aligned so that its complex elements are aligned
@@ -1176,8 +1177,12 @@ __global__ __launch_bounds__(kWgThreads, SMALL ? 2 : 1) void k_forward_wg(WgLaun
     const double2* tbuf = reinterpret_cast<const double2*>(a.tbuf);
     double2* VZ = reinterpret_cast<double2*>(X.DPM);
     double2* JS = reinterpret_cast<double2*>(X.K);
-    for (ItemSchedule sc = xcd_schedule(a.item_count); sc.next < sc.end; sc.next += sc.step) {
-        const int item = sc.next;
+    int probe = 0;
+    for (int par = 0;; par ^= 1) {
+        if (threadIdx.x == 0) S.unit[par] = queue_take(a.queue, a.item_count, probe);
+        __syncthreads();
+        const int item = S.unit[par];
+        if (item < 0) break;
         const BlockItem it = a.tb.blocks[a.item_begin + item];
         const ModelDev md = a.tb.models[it.model];
         const int n = md.n;
@@ -1285,9 +1290,17 @@ __global__ __launch_bounds__(kWgThreads, SMALL ? 2 : 1) void k_adjoint_wg(WgLaun
     const double delta = 1e-5 * scl;
     const WgScratch X = wg_scratch(reinterpret_cast<double2*>(a.scratch), a.slot_elems, blockIdx.x);
     const double2* tbuf = reinterpret_cast<const double2*>(a.tbuf);
-    for (ItemSchedule sc = xcd_schedule(a.item_count); sc.next < sc.end; sc.next += sc.step) {
-        const int item = sc.next;
+    const int units = a.item_count * a.unit_parts;
+    int probe = 0;
+    for (int par = 0;; par ^= 1) {
+        if (threadIdx.x == 0) S.unit[par] = queue_take(a.queue, units, probe);
+        __syncthreads();
+        const int unit = S.unit[par];
+        if (unit < 0) break;
+        const int item = unit / a.unit_parts;
+        const int kk0 = (unit - item * a.unit_parts) * a.unit_k;
         const BlockItem it = a.tb.blocks[a.item_begin + item];
+        const int kk1 = min(it.count, kk0 + a.unit_k);
         const ModelDev md = a.tb.models[it.model];
         const int n = md.n;
         const long long nn = (long long)n * n;
@@ -1297,7 +1310,7 @@ __global__ __launch_bounds__(kWgThreads, SMALL ? 2 : 1) void k_adjoint_wg(WgLaun
         const double* ef = a.e_fermi + md.f_off;
         const double* sb = a.sbar + md.f_off;
         const double invN = 1.0 / (double)md.Nk;
-        for (int kk = 0; kk < it.count; ++kk) {
+        for (int kk = kk0; kk < kk1; ++kk) {
             const bool ok = wg_eigen_velocities<SMALL>(S, X, md, T0, T1, r0, it.i0 + kk, a.max_iter);
             if (!ok) atomicOr(a.status, kStatNoConv);
             const double2* A = X.VX;
@@ -1436,6 +1449,7 @@ long long wg_slot_elems(int nmax) { return 7LL * nmax * nmax; }
 
 hipError_t launch_forward_wg(const WgLaunch& L, int np, hipStream_t s) {
     if (L.item_count <= 0) return hipSuccess;
+    if (!L.queue) return hipErrorInvalidValue;
     hipError_t e = wg_attrs();
     if (e != hipSuccess) return e;
     const int grid = L.item_count < L.max_groups ? L.item_count : L.max_groups;
@@ -1455,9 +1469,11 @@ hipError_t launch_forward_wg(const WgLaunch& L, int np, hipStream_t s) {
 
 hipError_t launch_adjoint_wg(const WgLaunch& L, int np, hipStream_t s) {
     if (L.item_count <= 0) return hipSuccess;
+    if (!L.queue || L.unit_k < 1 || L.unit_parts < 1) return hipErrorInvalidValue;
     hipError_t e = wg_attrs();
     if (e != hipSuccess) return e;
-    const int grid = L.item_count < L.max_groups ? L.item_count : L.max_groups;
+    const int units = L.item_count * L.unit_parts;
+    const int grid = units < L.max_groups ? units : L.max_groups;
     if (np <= 64)
         hipLaunchKernelGGL(k_adjoint_wg<true>, dim3(grid), dim3(kWgThreads), kWgSmallLds, s, L);
     else
