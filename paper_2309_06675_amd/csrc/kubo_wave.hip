@@ -255,10 +255,14 @@ __device__ void wave_tridiag(WaveLds<NP>& S, int n, double& d_lane, double& e_la
             e_lane = 0.0;
         }
     }
-    // reflectors back to LDS for the back-transformation
+    // reflectors back to LDS for the back-transformation, with zeros on and above
+    // the diagonal and in the padding rows, so that column k of S.P is v_k
+    // exactly (no masking of its rows when it is applied)
+    if (i < NP) {
 #pragma unroll
-    for (int jj = 0; jj < HW; ++jj)
-        if (row_ok && 2 * jj + h < i) S.P[i * LD + 2 * jj + h] = a[jj];
+        for (int jj = 0; jj < HW; ++jj)
+            S.P[i * LD + 2 * jj + h] = (row_ok && 2 * jj + h < i) ? a[jj] : c_make(0.0, 0.0);
+    }
     __syncthreads();
 }
 
@@ -565,8 +569,9 @@ __device__ void wave_twisted(const WaveLds<NP>& S, int n, double& lam, double pi
 
 // U <- H_0 H_1 ... H_{n-2} Z in registers: lane 2c + h holds rows 2 jj + h
 // of column c in u[jj] (Z on entry); the reflectors are read from S.P
-// (column k below the diagonal) as broadcasts, and groups of four slots whose
-// eight rows are all above the reflector are skipped.
+// (column k, zero on and above the diagonal and in the padding rows) as
+// broadcasts, and groups of four slots whose eight rows are all above the
+// reflector are skipped.
 template <int NP>
 __device__ void wave_backtransform(const WaveLds<NP>& S, int n, double2 (&u)[NP / 2]) {
     constexpr int LD = WaveLds<NP>::LD;
@@ -583,11 +588,7 @@ __device__ void wave_backtransform(const WaveLds<NP>& S, int n, double2 (&u)[NP 
             for (int t = 0; t < 4; ++t) vr[4 * gq + t] = c_make(0.0, 0.0);
             if (8 * gq + 7 > k) {  // some row of this group of four slots is below the reflector's top
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const int r = 2 * (4 * gq + t) + h;
-                    const double2 x = S.P[r * LD + k];
-                    vr[4 * gq + t] = (r > k && r < n) ? x : c_make(0.0, 0.0);
-                }
+                for (int t = 0; t < 4; ++t) vr[4 * gq + t] = S.P[(2 * (4 * gq + t) + h) * LD + k];
 #pragma unroll
                 for (int t = 0; t < 4; ++t) y = c_fmac(vr[4 * gq + t], u[4 * gq + t], y);
             }
