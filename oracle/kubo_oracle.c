@@ -38,6 +38,16 @@
  * Hall conductivity (spin current Js_x = (s_z v_x + v_x s_z)/2 with a diagonal
  * s_z, field along y).
  *
+ * oracle_ahc_gf evaluates the Green's-function form the paper names for
+ * systems with impurities (matrix inverses in place of eigenvalues; remark
+ * after Eq. (3)), with a constant scattering rate gamma:
+ *   G        = ((i (w + gamma) + mu) I - H(k))^{-1}      (explicit inverse)
+ *   sigma_j  = (1/N_k) sum_k sum_l c_l Im{ Tr[G v_x G G v_y] - Tr[G v_y G G v_x] } / (2 pi)
+ * at mu = E_F[j] and w = omega_l (> 0) for caller-given nodes and weights c_l
+ * of a quadrature over the half line w > 0.  With gamma = 0 the w-integral
+ * equals -sum_n theta(mu - E_n) Omega_n(eta = 0), i.e. Eqs. (2)-(3) at zero
+ * temperature (residues of the poles at w = i (mu - E_n)).
+ *
  * The reference gradient (oracle_ahc_grad) is derived in the design notes;
  * the paper has no adjoint.  It uses the divided-difference form of the
  * eigenvector term so that it stays finite through degeneracies.
@@ -645,6 +655,163 @@ int oracle_ahc_tensor(int n, int nR, const int* R, const double* t, const int* g
 }
 
 /* Smallest and largest eigenvalue of H(k) over the slab of the grid. */
+/* ------------------------------------------------------------------ */
+/* Green's-function form (one explicit inverse per k, mu and node).     */
+/* ------------------------------------------------------------------ */
+
+/* Ainv = A^{-1} by Gauss-Jordan elimination on [A | I] with partial (row)
+ * pivoting; A is destroyed.  Returns -1 for an exactly singular pivot. */
+static int cinv(int n, cplx* A, cplx* Ainv) {
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) Ainv[i * n + j] = (i == j) ? 1.0 : 0.0;
+    for (int p = 0; p < n; ++p) {
+        int best = p;
+        for (int i = p + 1; i < n; ++i)
+            if (cabs(A[i * n + p]) > cabs(A[best * n + p])) best = i;
+        if (A[best * n + p] == 0.0) return -1;
+        if (best != p)
+            for (int j = 0; j < n; ++j) {
+                cplx x = A[p * n + j];
+                A[p * n + j] = A[best * n + j];
+                A[best * n + j] = x;
+                x = Ainv[p * n + j];
+                Ainv[p * n + j] = Ainv[best * n + j];
+                Ainv[best * n + j] = x;
+            }
+        cplx d = 1.0 / A[p * n + p];
+        for (int j = 0; j < n; ++j) {
+            A[p * n + j] *= d;
+            Ainv[p * n + j] *= d;
+        }
+        for (int i = 0; i < n; ++i) {
+            if (i == p) continue;
+            cplx f = A[i * n + p];
+            if (f == 0.0) continue;
+            for (int j = 0; j < n; ++j) {
+                A[i * n + j] -= f * A[p * n + j];
+                Ainv[i * n + j] -= f * Ainv[p * n + j];
+            }
+        }
+    }
+    return 0;
+}
+
+/* C = A B (n x n, row-major) */
+static void cmatmul(int n, const cplx* A, const cplx* B, cplx* C) {
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            cplx s = 0.0;
+            for (int k = 0; k < n; ++k) s += A[i * n + k] * B[k * n + j];
+            C[i * n + j] = s;
+        }
+}
+
+static cplx ctrace(int n, const cplx* A) {
+    cplx s = 0.0;
+    for (int i = 0; i < n; ++i) s += A[i * n + i];
+    return s;
+}
+
+/* sigma[nF] as defined at the top of this file; sabs[nF] (optional) is the same
+ * sum with |Tr[..]| + |Tr[..]| in place of Im{..}, a scale for rounding. */
+int oracle_ahc_gf(int n, int nR, const int* R, const double* t, const int* grid, long k_begin,
+                  long k_count, int nF, const double* EF, double gamma, int nw,
+                  const double* omega, const double* weight, double* sigma, double* sabs,
+                  int nthreads) {
+    long Nk = (long)grid[0] * grid[1] * grid[2];
+    long nchunk = (k_count + ORACLE_KCHUNK - 1) / ORACLE_KCHUNK;
+    double* csum = calloc((size_t)nchunk * nF, sizeof(double));
+    double* cabsum = calloc((size_t)nchunk * nF, sizeof(double));
+    int bad = 0;
+    const double inv2pi = 1.0 / (2.0 * M_PI);
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel
+    {
+        size_t nn = (size_t)n * n;
+        cplx* phase = malloc((size_t)nR * sizeof(cplx));
+        cplx* H = malloc(nn * sizeof(cplx));
+        cplx* vx = malloc(nn * sizeof(cplx));
+        cplx* vy = malloc(nn * sizeof(cplx));
+        cplx* A = malloc(nn * sizeof(cplx));
+        cplx* G = malloc(nn * sizeof(cplx));
+        cplx* X = malloc(nn * sizeof(cplx));
+        cplx* Y = malloc(nn * sizeof(cplx));
+        cplx* M1 = malloc(nn * sizeof(cplx));
+        cplx* M2 = malloc(nn * sizeof(cplx));
+        nsum* acc = malloc((size_t)nF * sizeof(nsum));
+        nsum* aab = malloc((size_t)nF * sizeof(nsum));
+#pragma omp for schedule(dynamic, 1)
+        for (long c = 0; c < nchunk; ++c) {
+            for (int j = 0; j < nF; ++j) {
+                acc[j].s = acc[j].c = 0.0;
+                aab[j].s = aab[j].c = 0.0;
+            }
+            long kb = k_begin + c * ORACLE_KCHUNK;
+            long ke = kb + ORACLE_KCHUNK;
+            if (ke > k_begin + k_count) ke = k_begin + k_count;
+            for (long f = kb; f < ke; ++f) {
+                long i0, i1, i2;
+                flat_to_ijk(f, grid, &i0, &i1, &i2);
+                grid_phases(nR, R, grid, i0, i1, i2, phase);
+                build_hk(n, nR, R, (const cplx*)t, phase, H, vx, vy);
+                for (int j = 0; j < nF; ++j)
+                    for (int l = 0; l < nw; ++l) {
+                        const cplx z = I * (omega[l] + gamma) + EF[j];
+                        for (int a = 0; a < n; ++a)
+                            for (int b = 0; b < n; ++b)
+                                A[a * n + b] = ((a == b) ? z : 0.0) - H[a * n + b];
+                        if (cinv(n, A, G) != 0) {
+#pragma omp atomic write
+                            bad = 1;
+                            continue;
+                        }
+                        /* Tr[G v_x G G v_y] = Tr[(G v_x G)(G v_y)], and x <-> y */
+                        cmatmul(n, G, vx, X);
+                        cmatmul(n, G, vy, Y);
+                        cmatmul(n, X, G, M1);
+                        cmatmul(n, M1, Y, M2);
+                        const cplx t1 = ctrace(n, M2);
+                        cmatmul(n, Y, G, M1);
+                        cmatmul(n, M1, X, M2);
+                        const cplx t2 = ctrace(n, M2);
+                        nadd(&acc[j], weight[l] * cimag(t1 - t2) * inv2pi);
+                        nadd(&aab[j], fabs(weight[l]) * (cabs(t1) + cabs(t2)) * inv2pi);
+                    }
+            }
+            for (int j = 0; j < nF; ++j) {
+                csum[c * nF + j] = nval(&acc[j]);
+                cabsum[c * nF + j] = nval(&aab[j]);
+            }
+        }
+        free(phase);
+        free(H);
+        free(vx);
+        free(vy);
+        free(A);
+        free(G);
+        free(X);
+        free(Y);
+        free(M1);
+        free(M2);
+        free(acc);
+        free(aab);
+    }
+    for (int j = 0; j < nF; ++j) {
+        nsum s = {0.0, 0.0}, sa = {0.0, 0.0};
+        for (long c = 0; c < nchunk; ++c) {
+            nadd(&s, csum[c * nF + j]);
+            nadd(&sa, cabsum[c * nF + j]);
+        }
+        sigma[j] = nval(&s) / (double)Nk;
+        if (sabs) sabs[j] = nval(&sa) / (double)Nk;
+    }
+    free(csum);
+    free(cabsum);
+    return bad ? -1 : 0;
+}
+
 int oracle_band_range(int n, int nR, const int* R, const double* t, const int* grid, double* emin,
                       double* emax, int nthreads) {
     long Nk = (long)grid[0] * grid[1] * grid[2];

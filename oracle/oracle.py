@@ -57,6 +57,9 @@ def lib():
         L.oracle_ahc_tensor.argtypes = [ctypes.c_int, ctypes.c_int, _ip, _dp, _ip, ctypes.c_long,
                                         ctypes.c_long, ctypes.c_int, _dp, ctypes.c_double,
                                         ctypes.c_double, _dp, _dp, _dp, _dp, ctypes.c_int]
+        L.oracle_ahc_gf.argtypes = [ctypes.c_int, ctypes.c_int, _ip, _dp, _ip, ctypes.c_long,
+                                    ctypes.c_long, ctypes.c_int, _dp, ctypes.c_double,
+                                    ctypes.c_int, _dp, _dp, _dp, _dp, ctypes.c_int]
         L.oracle_band_range.argtypes = [ctypes.c_int, ctypes.c_int, _ip, _dp, _ip, _dp, _dp,
                                         ctypes.c_int]
         L.oracle_ahc_grad.argtypes = [ctypes.c_int, ctypes.c_int, _ip, _dp, _ip, ctypes.c_long,
@@ -172,6 +175,41 @@ def ahc_tensor(t, R, grid, e_fermi, eta, kT, spin=None, k_begin=0, k_count=None,
     if rc != 0:
         raise RuntimeError("oracle eigensolver did not converge")
     return (sig, np.maximum(sabs, sband)) if with_sabs else sig
+
+
+def ahc_gf(t, R, grid, e_fermi, gamma, omega, weight, k_begin=0, k_count=None, nthreads=0,
+           with_sabs=False):
+    """[nF]: the Green's-function form of sigma_xy (definition at the top of
+    kubo_oracle.c) for a constant scattering rate gamma, with the half-line
+    w-integral replaced by the caller's nodes `omega` (> 0) and weights `weight`;
+    over a k-slab, normalised by the full grid.  with_sabs: also return the
+    rounding scale (the same sum of |Tr| terms)."""
+    t, R, n, nR = _model(t, R)
+    grid = _c(grid, np.int32)
+    Nk = int(np.prod(grid.astype(np.int64)))
+    if k_count is None:
+        k_count = Nk - k_begin
+    EF = _c(np.atleast_1d(e_fermi), np.float64)
+    om = _c(np.atleast_1d(omega), np.float64)
+    wt = _c(np.atleast_1d(weight), np.float64)
+    assert om.shape == wt.shape
+    sig = np.zeros(EF.size)
+    sabs = np.zeros(EF.size)
+    rc = lib().oracle_ahc_gf(n, nR, _ptr(R, _ip), _ptr(t, _dp), _ptr(grid, _ip), int(k_begin),
+                             int(k_count), EF.size, _ptr(EF, _dp), float(gamma), om.size,
+                             _ptr(om, _dp), _ptr(wt, _dp), _ptr(sig, _dp), _ptr(sabs, _dp),
+                             int(nthreads))
+    if rc != 0:
+        raise RuntimeError("oracle: singular matrix in the Green's function")
+    return (sig, sabs) if with_sabs else sig
+
+
+def half_line_rule(m, scale=1.0):
+    """Nodes and weights for the integral over w in (0, inf): Gauss-Legendre on
+    u in (-1, 1) mapped by w = scale tan(pi (u + 1) / 4)."""
+    u, c = np.polynomial.legendre.leggauss(int(m))
+    th = 0.25 * np.pi * (u + 1.0)
+    return scale * np.tan(th), scale * 0.25 * np.pi * c / np.cos(th) ** 2
 
 
 def band_range(t, R, grid, nthreads=0):
