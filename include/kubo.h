@@ -159,6 +159,34 @@ kubo_status kubo_ahc_tensor(kubo_plan_t plan, const double* t, const double* e_f
                             double kT, const double* spin, double* sigma, void* workspace,
                             size_t workspace_bytes, void* stream);
 
+/* most quadrature nodes of one kubo_ahc_gf call */
+#define KUBO_GF_MAX_NODES 65536
+
+/*
+ * kubo_ahc_gf -- the Green's-function form of sigma_xy, which the paper names
+ * (remark after Eq. (3)) for systems with impurities: matrix inverses in place of
+ * the eigendecomposition.  With a constant scattering rate gamma,
+ *   G(w)       = ((i (w + gamma) + E_F[j]) I - H(k))^{-1}
+ *   sigma[j]   = (1/N_k) sum_k sum_l weight[l] Im{Tr[G v_x G G v_y] - Tr[G v_y G G v_x]} / (2 pi)
+ * with G = G(omega[l]): a quadrature over w > 0 given by the caller.  With
+ * gamma = 0 and a converged quadrature this is kubo_ahc's sigma_xy at eta = 0,
+ * kT = 0 (the residues of the poles at w = i (E_F - E_n) give Eq. (3)).
+ *   t, e_fermi, workspace as for kubo_ahc; the plan may be any plan of models
+ *              with n_orb <= 32 (else KUBO_E_UNSUPPORTED)
+ *   gamma      >= 0 (finite)
+ *   omega      device, double [n_omega]: the nodes; omega[l] + gamma > 0 keeps
+ *              every G finite (a zero would be reported as KUBO_E_NONFINITE)
+ *   weight     device, double [n_omega]: the weights
+ *   n_omega    1 <= n_omega <= KUBO_GF_MAX_NODES
+ *   sigma      device, double [n_models][n_fermi], overwritten
+ * One inverse (Gauss-Jordan elimination, no pivoting: i (w + gamma) + E_F - H has
+ * the positive definite part w + gamma along i) and four matrix products per
+ * k-point, Fermi level and node.  Errors: as kubo_ahc.
+ */
+kubo_status kubo_ahc_gf(kubo_plan_t plan, const double* t, const double* e_fermi, double gamma,
+                        const double* omega, const double* weight, int32_t n_omega, double* sigma,
+                        void* workspace, size_t workspace_bytes, void* stream);
+
 /*
  * kubo_ahc_backward -- gradient of L = sum_{m,j} sigma_bar[m][j] sigma[m][j]
  * with respect to every hopping: grad_t = dL/dRe t + i dL/dIm t (the
@@ -193,7 +221,8 @@ const char* kubo_status_string(kubo_status status);
  * kubo_plan_kernel_time -- device time of the per-k kernels recorded under
  * KUBO_F_TIMING since the last reset.  which = 0: the forward per-k kernel
  * (Bloch sum, eigensolve, rotation, curvature and Fermi sums); which = 1: the
- * backward per-k kernel; which = 2: the per-k kernel of kubo_ahc_tensor.  Waits for the recorded events.  Outputs (each may
+ * backward per-k kernel; which = 2: the per-k kernel of kubo_ahc_tensor; which
+ * = 3: the per-k kernel of kubo_ahc_gf.  Waits for the recorded events.  Outputs (each may
  * be NULL): total_ms, the number of launches, and the k-points they covered.
  * reset != 0 forgets the records afterwards.  KUBO_E_INVALID for a NULL plan
  * or a bad which; KUBO_E_HIP if an event query fails.

@@ -657,6 +657,47 @@ kubo_status enqueue_forward(kubo_plan_s* P, const double* t, const double* ef, d
     return KUBO_OK;
 }
 
+// The Green's-function form: step 1 as in the forward, then k_gf per size class.
+kubo_status enqueue_gf(kubo_plan_s* P, const double* t, const double* ef, double gamma,
+                       const double* omega, const double* weight, int n_omega, double* sigma,
+                       unsigned char* ws, hipStream_t s) {
+    const Tables tb = device_tables(P, ws, false);
+    unsigned* status = reinterpret_cast<unsigned*>(ws);
+    double* tp = reinterpret_cast<double*>(ws + P->off_tp);
+    double* tbuf = reinterpret_cast<double*>(ws + P->off_tbuf);
+    double* partial = reinterpret_cast<double*>(ws + P->off_partial);
+    unsigned* queues = reinterpret_cast<unsigned*>(ws + P->off_queues);
+    HIP_TRY(launch_clear(status, queues, 8 * P->n_queues, s));
+    HIP_TRY(launch_hermproj(tb, P->n_models, P->t_elems, t, tp, s));
+    for (size_t ci = 0; ci < P->fwd.chunks.size(); ++ci) {
+        const Chunk& c = P->fwd.chunks[ci];
+        HIP_TRY(launch_pencil(tb, c.pgroup_begin, c.pgroup_count, P->max_nn, tp, tbuf, false, s));
+        for (int k = 0; k < kNumClasses; ++k) {
+            if (c.cls[k].count == 0) continue;
+            TimedScope ts(P, s, 3, c.cls_kpts[k]);
+            GfLaunch L{};
+            L.tb = tb;
+            L.tbuf = tbuf;
+            L.e_fermi = ef;
+            L.omega = omega;
+            L.weight = weight;
+            L.partial = partial;
+            L.status = status;
+            L.queue = queues + 8 * (ci * kNumClasses + k);
+            L.gamma = gamma;
+            L.nF = P->nF;
+            L.n_omega = n_omega;
+            L.item_begin = c.cls[k].begin;
+            L.item_count = c.cls[k].count;
+            L.max_groups = kCUs;  // one workgroup per CU (84.5 KB of LDS)
+            HIP_TRY(launch_gf(L, s));
+            ts.finish();
+        }
+    }
+    HIP_TRY(launch_reduce(tb, P->n_models, P->nF, 1, partial, sigma, status, s));
+    return KUBO_OK;
+}
+
 kubo_status enqueue_backward(kubo_plan_s* P, const double* t, const double* ef, double eta,
                              double kT, const double* sbar, double* grad, unsigned char* ws,
                              hipStream_t s) {
@@ -833,6 +874,21 @@ kubo_status kubo_ahc_tensor(kubo_plan_t plan, const double* t, const double* e_f
                              true, true, spin);
 }
 
+kubo_status kubo_ahc_gf(kubo_plan_t plan, const double* t, const double* e_fermi, double gamma,
+                        const double* omega, const double* weight, int32_t n_omega, double* sigma,
+                        void* workspace, size_t workspace_bytes, void* stream) {
+    if (!plan || !t || !e_fermi || !omega || !weight || !sigma) return KUBO_E_INVALID;
+    if (!finite_nonneg(gamma) || n_omega < 1 || n_omega > KUBO_GF_MAX_NODES) return KUBO_E_INVALID;
+    for (const auto& md : plan->models)
+        if (md.n > 32) return KUBO_E_UNSUPPORTED;
+    if (!workspace || workspace_bytes < plan->total) return KUBO_E_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    unsigned char* ws = static_cast<unsigned char*>(workspace);
+    kubo_status st = ensure_tables(plan, workspace, s);
+    if (st != KUBO_OK) return st;
+    return enqueue_gf(plan, t, e_fermi, gamma, omega, weight, n_omega, sigma, ws, s);
+}
+
 kubo_status kubo_ahc_backward(kubo_plan_t plan, const double* t, const double* e_fermi,
                               double eta, double kT, const double* sigma_bar, double* grad_t,
                               void* workspace, size_t workspace_bytes, void* stream) {
@@ -874,7 +930,7 @@ kubo_status kubo_plan_device_status(kubo_plan_t plan, const void* workspace, voi
 
 kubo_status kubo_plan_kernel_time(kubo_plan_t plan, int32_t which, double* total_ms,
                                   int64_t* launches, int64_t* k_points, int32_t reset) {
-    if (!plan || which < 0 || which > 2) return KUBO_E_INVALID;
+    if (!plan || which < 0 || which > 3) return KUBO_E_INVALID;
     double ms = 0.0;
     long long nl = 0, kp = 0;
     for (const auto& r : plan->trec) {

@@ -52,6 +52,24 @@ struct WgLaunch {
     int unit_k, unit_parts;
 };
 
+// The Green's-function form (n <= 32): one workgroup per k-point, every item of
+// the list has n <= 32 whatever its size class.
+struct GfLaunch {
+    Tables tb;
+    const double* tbuf;
+    const double* e_fermi;
+    const double* omega;   // [n_omega] nodes of the half-line quadrature (device)
+    const double* weight;  // [n_omega] its weights (device)
+    double* partial;       // [slot][nF]
+    unsigned* status;
+    unsigned* queue;       // this launch's eight work-queue counters, zero at its start
+    double gamma;
+    int nF, n_omega;
+    int item_begin, item_count;
+    int max_groups;
+};
+hipError_t launch_gf(const GfLaunch& L, hipStream_t s);
+
 long long wg_slot_elems(int nmax);
 // np: the size class (64: n <= 64, 128: n <= 128)
 hipError_t launch_forward_wg(const WgLaunch& L, int np, hipStream_t s);

@@ -41,9 +41,10 @@ KUBO_F_DEBUG_SWEEPCAP = 0x100
 
 EXPORTED = ("kubo_plan", "kubo_ahc", "kubo_ahc_backward", "kubo_plan_device_status",
             "kubo_plan_destroy", "kubo_status_string", "kubo_plan_info", "kubo_plan_kernel_time",
-            "kubo_ahc_noalloc", "kubo_ahc_tensor")
+            "kubo_ahc_noalloc", "kubo_ahc_tensor", "kubo_ahc_gf")
 
 KUBO_NOALLOC_MAX_BYTES = 64 << 20
+KUBO_GF_MAX_NODES = 65536
 KUBO_DEVICE_NOCONV = 0x1
 KUBO_DEVICE_NONFINITE = 0x2
 
@@ -100,6 +101,9 @@ def lib() -> ctypes.CDLL:
         L.kubo_plan_kernel_time.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                             ctypes.POINTER(ctypes.c_int64),
                                             ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]
+        L.kubo_ahc_gf.restype = ctypes.c_int
+        L.kubo_ahc_gf.argtypes = [vp, vp, vp, ctypes.c_double, vp, vp, ctypes.c_int32, vp, vp,
+                                  ctypes.c_size_t, vp]
         L.kubo_ahc_noalloc.restype = ctypes.c_int
         L.kubo_ahc_noalloc.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_double, vp, vp, vp]
         L.kubo_plan_info.restype = ctypes.c_int
@@ -144,6 +148,12 @@ def kubo_ahc_tensor(plan, t_ptr: int, ef_ptr: int, eta: float, kT: float, spin_p
                     sigma_ptr: int, ws_ptr: int, ws_bytes: int, stream: int) -> int:
     return lib().kubo_ahc_tensor(plan, t_ptr, ef_ptr, float(eta), float(kT), spin_ptr, sigma_ptr,
                                  ws_ptr, int(ws_bytes), stream)
+
+
+def kubo_ahc_gf(plan, t_ptr: int, ef_ptr: int, gamma: float, omega_ptr: int, weight_ptr: int,
+                n_omega: int, sigma_ptr: int, ws_ptr: int, ws_bytes: int, stream: int) -> int:
+    return lib().kubo_ahc_gf(plan, t_ptr, ef_ptr, float(gamma), omega_ptr, weight_ptr,
+                             int(n_omega), sigma_ptr, ws_ptr, int(ws_bytes), stream)
 
 
 def kubo_ahc_backward(plan, t_ptr: int, ef_ptr: int, eta: float, kT: float, sbar_ptr: int,
@@ -324,6 +334,30 @@ class Plan:
                              out.data_ptr(), ws.data_ptr(), self.ws_bytes, stream)
         if st != KUBO_OK:
             raise KuboError(st, "kubo_ahc_tensor")
+        return out
+
+    def gf(self, t, e_fermi, gamma: float, omega, weight, out=None):
+        """[n_models, n_fermi] float64: the Green's-function form of sigma_xy with scattering
+        rate gamma, the w-integral over (0, inf) given by the nodes `omega` and weights
+        `weight` (contiguous float64 CUDA tensors of one length); models with n <= 32."""
+        import torch
+
+        self._check_t(t)
+        self._check_f(e_fermi, "e_fermi")
+        for x, name in ((omega, "omega"), (weight, "weight")):
+            if x.dtype != torch.float64 or not x.is_cuda or not x.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous float64 CUDA tensor")
+        if omega.numel() != weight.numel():
+            raise ValueError("omega and weight need the same length")
+        if out is None:
+            out = torch.empty(self.n_models, self.n_fermi, dtype=torch.float64, device=t.device)
+        ws = self.workspace()
+        stream = torch.cuda.current_stream(t.device).cuda_stream
+        st = kubo_ahc_gf(self.handle, t.data_ptr(), e_fermi.data_ptr(), gamma, omega.data_ptr(),
+                         weight.data_ptr(), omega.numel(), out.data_ptr(), ws.data_ptr(),
+                         self.ws_bytes, stream)
+        if st != KUBO_OK:
+            raise KuboError(st, "kubo_ahc_gf")
         return out
 
     def backward(self, t, e_fermi, eta: float, kT: float, sigma_bar, out=None):

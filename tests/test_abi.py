@@ -168,3 +168,31 @@ def test_tensor_plan_sizes_and_argument_checks():
     finally:
         kubo.kubo_plan_destroy(h)
         kubo.kubo_plan_destroy(h2)
+
+
+def test_gf_argument_checks():
+    """kubo_ahc_gf rejects bad scalars, NULL node arrays, too many nodes, a short workspace
+    and models with more than 32 orbitals before any device work."""
+    d, keep = _desc(n=4, grid=(4, 3, 2))
+    d40, keep40 = _desc(n=40, grid=(2, 2, 2))
+    st, h, wsb = kubo.kubo_plan([d], 3, kubo.KUBO_F_FORWARD_ONLY)
+    st2, h2, wsb2 = kubo.kubo_plan([d, d40], 3, kubo.KUBO_F_FORWARD_ONLY)
+    assert st == kubo.KUBO_OK and st2 == kubo.KUBO_OK
+    try:
+        fake = 0x1000  # never dereferenced
+        gf = kubo.kubo_ahc_gf
+        assert gf(h, fake, fake, -0.1, fake, fake, 4, fake, fake, wsb, None) == kubo.KUBO_E_INVALID
+        assert gf(h, fake, fake, float("nan"), fake, fake, 4, fake, fake, wsb, None) == \
+            kubo.KUBO_E_INVALID
+        assert gf(h, fake, fake, 0.1, 0, fake, 4, fake, fake, wsb, None) == kubo.KUBO_E_INVALID
+        assert gf(h, fake, fake, 0.1, fake, 0, 4, fake, fake, wsb, None) == kubo.KUBO_E_INVALID
+        assert gf(h, fake, fake, 0.1, fake, fake, 0, fake, fake, wsb, None) == kubo.KUBO_E_INVALID
+        assert gf(h, fake, fake, 0.1, fake, fake, kubo.KUBO_GF_MAX_NODES + 1, fake, fake, wsb,
+                  None) == kubo.KUBO_E_INVALID
+        assert gf(h, fake, fake, 0.1, fake, fake, 4, fake, fake, wsb - 1, None) == \
+            kubo.KUBO_E_WORKSPACE
+        assert gf(h2, fake, fake, 0.1, fake, fake, 4, fake, fake, wsb2, None) == \
+            kubo.KUBO_E_UNSUPPORTED
+    finally:
+        kubo.kubo_plan_destroy(h)
+        kubo.kubo_plan_destroy(h2)
