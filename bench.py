@@ -265,6 +265,63 @@ def measure_cfg4_slab(planes: int = 2, reps: int = 2):
                      "backward": bfk * kc / (bms / 1e3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS}}
 
 
+def gf_flops_per_k(n: int, n_R: int, nr0: int, n0: int, n_fermi: int, n_omega: int) -> float:
+    """Algorithmic flops per k-point of the Green's-function form: the pencil sums
+    (16 n_R n^2 per pencil, spread over its n0 points) and the full-matrix rho-sums of H, v_x,
+    v_y (24 nR0 n^2), then per Fermi level and node one inverse (8 n^3), four products
+    (32 n^3) and two traces (16 n^2)."""
+    return (16.0 * n_R * n * n / n0 + 24.0 * nr0 * n * n
+            + n_fermi * n_omega * (40.0 * n**3 + 16.0 * n * n))
+
+
+def measure_gf(reps: int = 3, n_fermi: int = 8, n_omega: int = 16, gamma: float = 0.01):
+    """The Green's-function form on the n_orb = 32 model (343 R) on a 32^3 grid: n_fermi of the
+    workload's Fermi levels, n_omega Gauss-Legendre nodes on (0, inf) (w = tan(pi (u + 1)/4)),
+    scattering rate gamma; median of `reps` passes."""
+    import torch
+
+    from paper_2309_06675_amd import kubo, synth
+
+    wl = synth.workload(1)
+    m = wl.models[0]
+    grid = (32, 32, 32)
+    nk = grid[0] * grid[1] * grid[2]
+    ef_all = fermi_levels(1, wl)[0]
+    ef = np.ascontiguousarray(ef_all[:: len(ef_all) // n_fermi][:n_fermi]).reshape(1, n_fermi)
+    u, c = np.polynomial.legendre.leggauss(n_omega)
+    th = 0.25 * np.pi * (u + 1.0)
+    om, wt = np.tan(th), 0.25 * np.pi * c / np.cos(th) ** 2
+    dev = "cuda:0"
+    stream = torch.cuda.current_stream(dev)
+    plan = kubo.Plan([m], grid=grid, n_fermi=n_fermi,
+                     flags=kubo.KUBO_F_FORWARD_ONLY | kubo.KUBO_F_TIMING, device=dev)
+    t = kubo.to_device_t([m], dev)
+    efd = torch.from_numpy(ef).to(dev)
+    omd = torch.from_numpy(om).to(dev)
+    wtd = torch.from_numpy(wt).to(dev)
+    sig = torch.empty(1, n_fermi, dtype=torch.float64, device=dev)
+    plan.gf(t, efd, gamma, omd, wtd, out=sig)
+    torch.cuda.synchronize()
+    plan.kernel_time(3, reset=True)
+    ms, alls = _timed_median(lambda: plan.gf(t, efd, gamma, omd, wtd, out=sig), reps, stream)
+    st = plan.device_status()
+    if st != kubo.KUBO_OK:
+        raise SystemExit(f"gf device status: {kubo.kubo_status_string(st)}")
+    k_ms, launches, kpts = plan.kernel_time(3)
+    fpk = gf_flops_per_k(m.n, m.n_R, n_rx(m), grid[0], n_fermi, n_omega)
+    fpk_kernel = fpk - 16.0 * m.n_R * m.n**2 / grid[0]
+    achieved = fpk_kernel * kpts / (k_ms / 1e3) / 1e12
+    print(f"gf {ms:.1f} ms", file=sys.stderr, flush=True)
+    return {"workload": f"gf_n32_R343_k32^3_F{n_fermi}_W{n_omega}_gamma{gamma:g}",
+            "k_points": nk, "reps": reps, "ms_median": ms, "ms_all": alls,
+            "k_points_per_s": nk / (ms / 1e3),
+            "kernel": "k_gf (one workgroup per k-point)",
+            "kernel_ms_per_pass": k_ms / reps, "flops_per_k": fpk,
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS},
+            "sigma_checksum": float(sig.sum().item())}
+
+
 def measure_large(adjoint: bool = True, parts: int = 16):
     """The n_orb = 128 workload over its whole 128^3 grid (forward at eta = 1e-3, adjoint at
     eta = 1e-2), enqueued as `parts` consecutive k-slabs (slabs add up exactly; each slab
@@ -436,7 +493,9 @@ def main(argv=None):
                     help="only run two elementwise FP64 kernels on MB megabytes (counter calibration)")
     ap.add_argument("--large", action="store_true",
                     help="only run the n_orb = 128 workload over its full grid and print it")
-    ap.add_argument("--legs", default="forward,adjoint,n128,batched,cpu",
+    ap.add_argument("--gf-reps", type=int, default=3,
+                    help="timed passes (median) of the Green's-function form (0 skips)")
+    ap.add_argument("--legs", default="forward,adjoint,n128,batched,gf,cpu",
                     help="comma-separated legs to run (forward is always run; for profiling)")
     args = ap.parse_args(argv)
     legs = set(args.legs.split(","))
@@ -558,6 +617,8 @@ def main(argv=None):
         out["adjoint"] = measure_adjoint_cfg3(args.adjoint_reps)
     if args.large_reps > 0 and "n128" in legs:
         out["n128_slab"] = measure_cfg4_slab(reps=args.large_reps)
+    if args.gf_reps > 0 and "gf" in legs:
+        out["gf"] = measure_gf(args.gf_reps)
     if args.batched_steps > 0 and "batched" in legs:
         out["batched"] = measure_batched(args.batched_steps, 1)
     if args.cpu_sample > 0 and "cpu" in legs:

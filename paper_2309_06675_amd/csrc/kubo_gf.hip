@@ -11,8 +11,9 @@
 // products per Fermi level and node.
 //
 // k_gf: one 256-thread workgroup per k-point.  H lives in registers (thread t
-// owns row t / 8, columns t % 8 + 8 q), v_x, v_y, G and the two products X = G v_x,
-// Y = G v_y in LDS (32 x 33 complex each, 84.5 KB: one workgroup per CU).  The
+// owns row t / 8, columns t % 8 + 8 q), v_x and v_y too, as the MFMA B operands of
+// the lane's quadrant column; G and the two products X = G v_x, Y = G v_y live in
+// LDS (32 x 33 complex each, 51 KB: two workgroups per CU).  The
 // inverse is Gauss-Jordan elimination without pivoting: (i (w + gamma) + mu) - H
 // times -i has the positive definite Hermitian part (w + gamma) I, so every
 // pivot is nonzero and elimination without pivoting is stable for it.  The four
@@ -36,8 +37,6 @@ constexpr int kGfLD = kGfN + 1;
 constexpr int kGfThreads = 256;
 
 struct GfLds {
-    double2 Vx[kGfN * kGfLD];
-    double2 Vy[kGfN * kGfLD];
     double2 G[kGfN * kGfLD];
     double2 X[kGfN * kGfLD];
     double2 Y[kGfN * kGfLD];
@@ -70,18 +69,36 @@ __device__ __forceinline__ void gf_mm(const double2* A, const double2* B, int r0
     }
 }
 
+// The same with B given as this lane's operands b[k0 / 4] = B[k0 + lane / 16][c0 + lane % 16].
+__device__ __forceinline__ void gf_mm_rb(const double2* A, const double2 (&b)[kGfN / 4], int r0,
+                                         int kmax, int lane, v4d& cr, v4d& ci) {
+    const int a_row = r0 + (lane & 15), kl = lane >> 4;
+#pragma unroll
+    for (int s = 0; s < kGfN / 4; ++s) {
+        if (4 * s < kmax) {
+            const double2 a = A[a_row * kGfLD + 4 * s + kl];
+            cr = mfma(a.x, b[s].x, cr);
+            cr = mfma(-a.y, b[s].y, cr);
+            ci = mfma(a.x, b[s].y, ci);
+            ci = mfma(a.y, b[s].x, ci);
+        }
+    }
+}
+
 __device__ __forceinline__ double gf_wave_sum(double v) {
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
 }
 
-// 1 / z
+// 1 / z: the hardware reciprocal estimate of |z|^2 and one Newton step
 __device__ __forceinline__ double2 c_recip(double2 z) {
-    const double d = 1.0 / fma(z.x, z.x, z.y * z.y);
+    const double m = fma(z.x, z.x, z.y * z.y);
+    double d = __builtin_amdgcn_rcp(m);
+    d = fma(d, fma(-m, d, 1.0), d);
     return c_make(z.x * d, -z.y * d);
 }
 
-__global__ __launch_bounds__(kGfThreads, 1) void k_gf(GfLaunch a) {
+__global__ __launch_bounds__(kGfThreads, 2) void k_gf(GfLaunch a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     GfLds& S = *reinterpret_cast<GfLds*>(smem_raw);
     const int tid = threadIdx.x;
@@ -109,7 +126,7 @@ __global__ __launch_bounds__(kGfThreads, 1) void k_gf(GfLaunch a) {
         const int kq = (n + 3) & ~3;  // inner extent of the products
         const bool quad_live = qr0 < n && qc0 < n;
         for (int kk = 0; kk < it.count; ++kk) {
-            // ---- step 1: H (registers), v_x and v_y (LDS) from the pencil partial sums
+            // ---- step 1: H, v_x and v_y (registers) from the pencil partial sums
             if (tid < md.nR0) S.ph[tid] = unit_phase((long long)(it.i0 + kk) * r0[tid], md.N0);
             __syncthreads();
             double2 h[4];
@@ -128,8 +145,16 @@ __global__ __launch_bounds__(kGfThreads, 1) void k_gf(GfLaunch a) {
                     }
                 }
                 h[q] = hv;
-                S.Vx[ri * kGfLD + j] = xv;
-                S.Vy[ri * kGfLD + j] = yv;
+                S.X[ri * kGfLD + j] = xv;  // v_x and v_y pass through the X and Y buffers
+                S.Y[ri * kGfLD + j] = yv;
+            }
+            __syncthreads();
+            double2 bx[kGfN / 4], by[kGfN / 4];
+#pragma unroll
+            for (int s4 = 0; s4 < kGfN / 4; ++s4) {
+                const int e = (4 * s4 + (lane >> 4)) * kGfLD + qc0 + (lane & 15);
+                bx[s4] = S.X[e];
+                by[s4] = S.Y[e];
             }
             __syncthreads();
             for (int fj = 0; fj < a.nF; ++fj) {
@@ -177,8 +202,8 @@ __global__ __launch_bounds__(kGfThreads, 1) void k_gf(GfLaunch a) {
                     {
                         v4d xr = {0.0, 0.0, 0.0, 0.0}, xi = xr, yr = xr, yi = xr;
                         if (quad_live) {
-                            gf_mm(S.G, S.Vx, qr0, qc0, kq, lane, xr, xi);
-                            gf_mm(S.G, S.Vy, qr0, qc0, kq, lane, yr, yi);
+                            gf_mm_rb(S.G, bx, qr0, kq, lane, xr, xi);
+                            gf_mm_rb(S.G, by, qr0, kq, lane, yr, yi);
                         }
 #pragma unroll
                         for (int q = 0; q < 4; ++q) {
