@@ -13,7 +13,7 @@
 // k_gf: one 256-thread workgroup per k-point.  H lives in registers (thread t
 // owns row t / 8, columns t % 8 + 8 q), v_x and v_y too, as the MFMA B operands of
 // the lane's quadrant column; G and the two products X = G v_x, Y = G v_y live in
-// LDS (32 x 33 complex each, 51 KB: two workgroups per CU).  The
+// LDS (32 x 33 complex each, 51 KB: three workgroups per CU).  The
 // inverse is Gauss-Jordan elimination without pivoting: (i (w + gamma) + mu) - H
 // times -i has the positive definite Hermitian part (w + gamma) I, so every
 // pivot is nonzero and elimination without pivoting is stable for it.  The four
@@ -98,7 +98,7 @@ __device__ __forceinline__ double2 c_recip(double2 z) {
     return c_make(z.x * d, -z.y * d);
 }
 
-__global__ __launch_bounds__(kGfThreads, 2) void k_gf(GfLaunch a) {
+__global__ __launch_bounds__(kGfThreads, 3) void k_gf(GfLaunch a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     GfLds& S = *reinterpret_cast<GfLds*>(smem_raw);
     const int tid = threadIdx.x;

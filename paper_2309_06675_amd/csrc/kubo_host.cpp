@@ -689,7 +689,7 @@ kubo_status enqueue_gf(kubo_plan_s* P, const double* t, const double* ef, double
             L.n_omega = n_omega;
             L.item_begin = c.cls[k].begin;
             L.item_count = c.cls[k].count;
-            L.max_groups = 2 * kCUs;  // two workgroups per CU (51 KB of LDS each)
+            L.max_groups = 3 * kCUs;  // three workgroups per CU (51 KB of LDS each)
             HIP_TRY(launch_gf(L, s));
             ts.finish();
         }
