@@ -98,6 +98,8 @@ __device__ __forceinline__ double2 c_recip(double2 z) {
     return c_make(z.x * d, -z.y * d);
 }
 
+}  // namespace
+
 __global__ __launch_bounds__(kGfThreads, 3) void k_gf(GfLaunch a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     GfLds& S = *reinterpret_cast<GfLds*>(smem_raw);
@@ -246,8 +248,6 @@ __global__ __launch_bounds__(kGfThreads, 3) void k_gf(GfLaunch a) {
         }
     }
 }
-
-}  // namespace
 
 hipError_t launch_gf(const GfLaunch& L, hipStream_t s) {
     if (L.item_count <= 0) return hipSuccess;
