@@ -64,7 +64,8 @@ typedef enum {
 
 /* One tight-binding model and the part of its k-grid to sum over. */
 typedef struct {
-    int32_t n_orb;        /* orbitals n (matrix size), 1 <= n <= 128 */
+    int32_t n_orb;        /* orbitals n (matrix size), 1 <= n <= 512; n > 128 runs the
+                             large-n pipeline (forward only, see kubo_plan) */
     int32_t n_R;          /* number of lattice vectors, >= 1 */
     const int32_t* R;     /* HOST array [n_R][3]; no duplicates, closed under R -> -R.
                              Copied by kubo_plan. */
@@ -113,7 +114,15 @@ typedef struct {
  * Larger chunks mean fewer launches and a larger workspace.
  * Errors: KUBO_E_INVALID for NULL pointers, n_orb < 1, n_R < 1, grid < 1,
  * duplicate R, an R whose negative is missing, a slab outside the grid or a
- * bad tile; KUBO_E_UNSUPPORTED for n_orb > 128.
+ * bad tile; KUBO_E_UNSUPPORTED for n_orb > 512, for more than 16 distinct R_x,
+ * and for a model with n_orb > 128 in a plan without KUBO_F_FORWARD_ONLY or with
+ * KUBO_F_TENSOR.  Models with 128 < n_orb <= 512 (the paper's large-N_d regime,
+ * end of its section on the vectorised implementation) run a pipeline that
+ * spreads each k-point over many workgroups: Householder reduction, bisection on
+ * the split tridiagonal matrix, tridiagonal eigenvectors, a compact-WY
+ * back-transformation and the rotations on batched matrix-core products; their
+ * per-k-point slices (about 12 n^2 complex elements each, for up to 256 k-points
+ * at a time) are part of the workspace.
  */
 kubo_status kubo_plan(kubo_plan_t* plan, const kubo_model_desc* models, int32_t n_models,
                       int32_t n_fermi, uint32_t flags, const kubo_tile* tiles, int32_t n_tiles,

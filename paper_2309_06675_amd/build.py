@@ -18,8 +18,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkubo.so")
 ARCH = os.environ.get("KUBO_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["kubo_device.hip", "kubo_wave.hip", "kubo_wg.hip", "kubo_gf.hip", "kubo_noalloc.hip",
-           "kubo_host.cpp"]
+SOURCES = ["kubo_device.hip", "kubo_wave.hip", "kubo_wg.hip", "kubo_gf.hip", "kubo_big.hip",
+           "kubo_noalloc.hip", "kubo_host.cpp"]
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}",

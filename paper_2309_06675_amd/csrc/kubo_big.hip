@@ -1,0 +1,694 @@
+// kubo_big.hip -- the large-n path (128 < n <= 512): the paper's matrix-parallel
+// regime for large N_d (end of its section on the vectorised implementation),
+// where one k-point's matrices are large enough to spread over many workgroups.
+//
+// A batch of k-points of one model (one k-point per work item) goes through a
+// pipeline of kernels, each over the whole batch; per k-point the matrices live
+// in a slice of the workspace (row-major, complex):
+//   k_big_build    H, v_x, v_y from the pencil partial sums (many workgroups per k)
+//   k_big_tridiag  Householder reduction to real tridiagonal T (one 1024-thread
+//                  workgroup per k; the trailing matrix in the slice, L2-resident)
+//   k_big_eig      T split into unreduced blocks where an off-diagonal is negligible,
+//                  then every eigenvalue by Sturm bisection within its block (a thread each)
+//   k_big_vec      eigenvectors of T: a twisted factorisation per isolated eigenvalue,
+//                  inverse iteration with reorthogonalisation for clustered ones
+//   k_big_tfac     T factors of the compact WY form of 32 Householder reflectors
+//   k_big_gemm     batched complex products on FP64 MFMA (64 x 64 tiles, many
+//                  workgroups per k): the back-transformation U = Q Z block by block
+//                  (W = V^+ Z, W' = T W, Z -= V W') and the rotations U^+ v U
+//   k_big_curv     band-pair curvature and the Fermi sums into the item's slot
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "kubo_cplx.h"
+#include "kubo_internal.h"
+#include "kubo_launch.h"
+
+namespace kubo {
+
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4d mfma(double a, double b, v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// the k-point slice of item b of a launch
+struct BigSlice {
+    double2 *H, *VX, *VY, *U, *X, *V, *W, *W2, *TF;
+    double *d, *e, *E, *piv;
+    double2* tau;
+    int* blk;  // per eigenvalue: block start (low 16 bits) and size (high 16 bits)
+};
+
+__device__ __forceinline__ BigSlice big_slice(const BigLaunch& a, int b) {
+    const BigLayout L = big_layout(a.n);
+    double2* base = reinterpret_cast<double2*>(a.scratch) + (long long)b * a.per_k;
+    double* dbl = reinterpret_cast<double*>(base);
+    BigSlice s;
+    s.H = base + L.H;
+    s.VX = base + L.VX;
+    s.VY = base + L.VY;
+    s.U = base + L.U;
+    s.X = base + L.X;
+    s.V = base + L.V;
+    s.W = base + L.W;    // kBigB x n
+    s.W2 = base + L.W2;  // kBigB x n
+    s.TF = base + L.TF;  // blocks x kBigB x kBigB
+    s.tau = base + L.tau;
+    s.d = dbl + L.d;
+    s.e = dbl + L.e;
+    s.E = dbl + L.E;
+    s.piv = dbl + L.piv;  // 6 n doubles per eigenvalue thread
+    s.blk = reinterpret_cast<int*>(dbl + L.blk);
+    return s;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int i = 0; i < nw; ++i) s += red[i];
+    return s;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// step 1: H, v_x, v_y of item b (grid: (element tiles, items))
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_big_build(BigLaunch a) {
+    __shared__ double2 ph[16];
+    const int b = blockIdx.y;
+    const BlockItem it = a.tb.blocks[a.item_begin + b];
+    const ModelDev md = a.tb.models[it.model];
+    const int n = a.n;
+    const long long nn = (long long)n * n;
+    const int* r0 = a.tb.r0val + md.r0_first;
+    if (threadIdx.x < md.nR0) ph[threadIdx.x] = unit_phase((long long)it.i0 * r0[threadIdx.x], md.N0);
+    __syncthreads();
+    const BigSlice s = big_slice(a, b);
+    const double2* T0 = reinterpret_cast<const double2*>(a.tbuf) + it.tbuf_off;
+    const double2* T1 = T0 + (long long)md.nR0 * nn;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nn;
+         e += (long long)gridDim.x * blockDim.x) {
+        double2 h = c_make(0.0, 0.0), x = c_make(0.0, 0.0), y = c_make(0.0, 0.0);
+        for (int rho = 0; rho < md.nR0; ++rho) {
+            const double2 t0 = T0[rho * nn + e], t1 = T1[rho * nn + e];
+            h = c_fma(t0, ph[rho], h);
+            x = c_fma(t0, c_scale((double)r0[rho], c_i(ph[rho])), x);
+            y = c_fma(t1, ph[rho], y);
+        }
+        s.H[e] = h;
+        s.VX[e] = x;
+        s.VY[e] = y;
+        s.V[e] = c_make(0.0, 0.0);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// step 2a: Householder reduction of H (Hermitian, full storage) to real
+// tridiagonal T = Q^+ H Q, Q = H_0 ... H_{n-2}, H_k = I - tau_k v_k v_k^+ with
+// v_k[k+1] = 1.  The reflectors go to V (column k, zero elsewhere), tau to tau,
+// the diagonal to d and the off-diagonal to e.  One workgroup per k-point.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_big_tridiag(BigLaunch a) {
+    __shared__ double2 v[kBigMaxN], w[kBigMaxN], p[kBigMaxN];
+    __shared__ double red[16];
+    __shared__ double2 sh_tau, sh_scal;
+    __shared__ double sh_beta;
+    const int b = blockIdx.x;
+    const int n = a.n;
+    const BigSlice s = big_slice(a, b);
+    double2* A = s.H;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int k = 0; k < n - 1; ++k) {
+        // column k below the diagonal
+        const int m = n - k - 1;  // rows k+1 .. n-1
+        double xn2 = 0.0;
+        for (int i = tid; i < m; i += nt) {
+            const double2 x = A[(long long)(k + 1 + i) * n + k];
+            v[i] = x;
+            if (i > 0) xn2 += x.x * x.x + x.y * x.y;
+        }
+        xn2 = block_sum(xn2, red);  // (contains barriers: v is visible after it)
+        if (tid == 0) {
+            const double2 alpha = v[0];
+            double beta;
+            double2 tau, scal;
+            if (xn2 == 0.0 && alpha.y == 0.0) {
+                beta = alpha.x;
+                tau = c_make(0.0, 0.0);
+                scal = c_make(0.0, 0.0);
+            } else {
+                const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn2);
+                beta = -copysign(nrm, alpha.x);
+                tau = c_make((beta - alpha.x) / beta, -alpha.y / beta);
+                const double ar = alpha.x - beta, ai = alpha.y;
+                const double den = 1.0 / (ar * ar + ai * ai);
+                scal = c_make(ar * den, -ai * den);
+            }
+            sh_beta = beta;
+            sh_tau = tau;
+            sh_scal = scal;
+            s.d[k] = A[(long long)k * n + k].x;
+            s.e[k] = beta;
+            s.tau[k] = tau;
+        }
+        __syncthreads();
+        const double2 tau = sh_tau, scal = sh_scal;
+        for (int i = tid; i < m; i += nt) {
+            const double2 vi = (i == 0) ? c_make(1.0, 0.0) : c_mul(v[i], scal);
+            v[i] = vi;
+            s.V[(long long)(k + 1 + i) * n + k] = vi;
+        }
+        __syncthreads();
+        if (tau.x == 0.0 && tau.y == 0.0) continue;
+        // p = A v over the trailing block; A Hermitian: p_i = sum_j conj(A_ji) v_j, read
+        // along rows j (consecutive threads, consecutive columns i)
+        for (int i = tid; i < m; i += nt) {
+            double2 acc = c_make(0.0, 0.0);
+            for (int j = 0; j < m; ++j)
+                acc = c_fmac(A[(long long)(k + 1 + j) * n + k + 1 + i], v[j], acc);
+            p[i] = acc;
+        }
+        __syncthreads();
+        double mu = 0.0;
+        for (int i = tid; i < m; i += nt) mu += v[i].x * p[i].x + v[i].y * p[i].y;
+        mu = block_sum(mu, red);
+        const double t2 = 0.5 * (tau.x * tau.x + tau.y * tau.y) * mu;
+        for (int i = tid; i < m; i += nt) w[i] = c_sub(c_mul(tau, p[i]), c_scale(t2, v[i]));
+        __syncthreads();
+        // A <- A - v w^+ - w v^+ on the trailing block
+        for (long long e = tid; e < (long long)m * m; e += nt) {
+            const int i = (int)(e / m), j = (int)(e - (long long)(e / m) * m);
+            double2& aij = A[(long long)(k + 1 + i) * n + k + 1 + j];
+            aij = c_rank2c(aij, v[i], w[j], w[i], v[j]);
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        s.d[n - 1] = A[(long long)(n - 1) * n + n - 1].x;
+        s.e[n - 1] = 0.0;
+        s.tau[n - 1] = c_make(0.0, 0.0);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// step 2b: eigenvalues.  T splits where |e_i| <= eps (|d_i| + |d_i+1|); within an
+// unreduced block every eigenvalue is simple, found by Sturm bisection on the
+// block (ratio form with a pivot floor) to 4 eps max|lambda|.  Thread j takes the
+// j-th eigenvalue in block order (eigenvalues are not sorted: nothing downstream
+// needs an order).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBigMaxN) void k_big_eig(BigLaunch a) {
+    __shared__ int bstart[kBigMaxN], bsize[kBigMaxN], boff[kBigMaxN];
+    __shared__ int nblk;
+    __shared__ double sh_lo, sh_hi, sh_emax;
+    const int b = blockIdx.x;
+    const int n = a.n;
+    const BigSlice s = big_slice(a, b);
+    const int j = threadIdx.x;
+    if (j == 0) {
+        double lo = 1e300, hi = -1e300, emax = 0.0;
+        int nb = 0, start = 0;
+        for (int i = 0; i < n; ++i) {
+            const double ep = (i > 0) ? fabs(s.e[i - 1]) : 0.0, en = (i < n - 1) ? fabs(s.e[i]) : 0.0;
+            lo = fmin(lo, s.d[i] - ep - en);
+            hi = fmax(hi, s.d[i] + ep + en);
+            emax = fmax(emax, en);
+            const bool cut = (i == n - 1) || en <= 2.220446049250313e-16 * (fabs(s.d[i]) + fabs(s.d[i + 1]));
+            if (cut) {
+                bstart[nb] = start;
+                bsize[nb] = i + 1 - start;
+                boff[nb] = start;
+                ++nb;
+                start = i + 1;
+            }
+        }
+        nblk = nb;
+        sh_lo = lo;
+        sh_hi = hi;
+        sh_emax = emax;
+    }
+    __syncthreads();
+    if (j >= n) return;
+    int bi = 0;
+    while (bi + 1 < nblk && boff[bi + 1] <= j) ++bi;
+    const int st = bstart[bi], m = bsize[bi], jl = j - st;
+    const double scale = fmax(fabs(sh_lo), fabs(sh_hi));
+    const double tol = 4.0 * 2.220446049250313e-16 * scale + 1e-300;
+    const double pivmin = 1e-290 * fmax(1.0, sh_emax * sh_emax);
+    double lo = sh_lo, hi = sh_hi;
+    bool ok = false;
+    for (int pass = 0; pass < 200; ++pass) {
+        if (hi - lo <= tol) {
+            ok = true;
+            break;
+        }
+        const double x = 0.5 * (lo + hi);
+        int cnt = 0;
+        double q = 1.0;
+        for (int i = st; i < st + m; ++i) {
+            const double e2 = (i > st) ? s.e[i - 1] * s.e[i - 1] : 0.0;
+            double qi = (s.d[i] - x) - ((i > st) ? e2 / q : 0.0);
+            if (fabs(qi) < pivmin) qi = -pivmin;
+            cnt += (qi < 0.0) ? 1 : 0;
+            q = qi;
+        }
+        if (cnt <= jl) lo = x;
+        else hi = x;
+    }
+    s.E[j] = 0.5 * (lo + hi);
+    s.blk[j] = st | (m << 16);
+    if (!ok) atomicOr(a.status, kStatNoConv);
+}
+
+// ---------------------------------------------------------------------------
+// step 2c: eigenvectors of T into Z (stored in U, real, column j, zero outside
+// the block).  An eigenvalue whose relative gap to its block neighbours is at
+// least kBigGap takes one twisted factorisation (error eps |T| / gap); a cluster
+// is solved by its first member's thread, member by member, with inverse
+// iteration from a fixed pseudo-random start (splitmix64 of the index) and
+// modified Gram-Schmidt against the cluster's earlier members after each solve.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double big_start(int j, int i) {
+    unsigned long long z = 0x9E3779B97F4A7C15ull * (unsigned long long)(j * 1315423911u + i + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+}
+
+// solve (T - lam I) y = x on rows [st, st+m) by Gaussian elimination with partial
+// pivoting (the tridiagonal LU keeps a second superdiagonal); y overwrites x.
+// u0, u1, u2, l: scratch of m doubles each.
+__device__ void big_tri_solve(const double* d, const double* e, int st, int m, double lam,
+                              double pivmin, double* x, double* u0, double* u1, double* u2,
+                              double* l, int* pv) {
+    // rows i: diag d_i - lam, sub/super e_i
+    double a0 = d[st] - lam, a1 = (m > 1) ? e[st] : 0.0, a2 = 0.0;
+    for (int i = 0; i < m - 1; ++i) {
+        const double sub = e[st + i];
+        const double b0 = d[st + i + 1] - lam, b1 = (i + 1 < m - 1) ? e[st + i + 1] : 0.0;
+        if (fabs(sub) > fabs(a0)) {  // swap rows i and i+1
+            pv[i] = 1;
+            u0[i] = sub;
+            u1[i] = b0;
+            u2[i] = b1;
+            const double f = a0 / sub;
+            l[i] = f;
+            a0 = a1 - f * b0;
+            a1 = a2 - f * b1;
+            a2 = 0.0;
+        } else {
+            pv[i] = 0;
+            if (fabs(a0) < pivmin) a0 = pivmin;
+            u0[i] = a0;
+            u1[i] = a1;
+            u2[i] = a2;
+            const double f = sub / a0;
+            l[i] = f;
+            a0 = b0 - f * a1;
+            a1 = b1;
+            a2 = 0.0;
+        }
+    }
+    if (fabs(a0) < pivmin) a0 = pivmin;
+    u0[m - 1] = a0;
+    u1[m - 1] = 0.0;
+    u2[m - 1] = 0.0;
+    // forward: apply the row swaps and multipliers to x
+    for (int i = 0; i < m - 1; ++i) {
+        if (pv[i]) {
+            const double t = x[i];
+            x[i] = x[i + 1];
+            x[i + 1] = t - l[i] * x[i];
+        } else {
+            x[i + 1] -= l[i] * x[i];
+        }
+    }
+    // back substitution with the upper factor (bandwidth 3)
+    for (int i = m - 1; i >= 0; --i) {
+        double r = x[i];
+        if (i + 1 < m) r -= u1[i] * x[i + 1];
+        if (i + 2 < m) r -= u2[i] * x[i + 2];
+        x[i] = r / u0[i];
+    }
+}
+
+__global__ __launch_bounds__(kBigMaxN) void k_big_vec(BigLaunch a) {
+    const int b = blockIdx.x;
+    const int n = a.n;
+    const BigSlice s = big_slice(a, b);
+    const int j = threadIdx.x;
+    for (long long e = j; e < (long long)n * n; e += blockDim.x) s.U[e] = c_make(0.0, 0.0);
+    __syncthreads();
+    if (j >= n) return;
+    const int st = s.blk[j] & 0xffff, m = s.blk[j] >> 16;
+    const double lam = s.E[j];
+    double span = 0.0, emax = 0.0;
+    for (int i = st; i < st + m; ++i) {
+        span = fmax(span, fabs(s.d[i]) + ((i > st) ? fabs(s.e[i - 1]) : 0.0) + ((i < st + m - 1) ? fabs(s.e[i]) : 0.0));
+        emax = fmax(emax, (i < st + m - 1) ? fabs(s.e[i]) : 0.0);
+    }
+    const double pivmin = 1e-290 * fmax(1.0, emax * emax);
+    const double gapmin = kBigGap * fmax(span, 1e-300);
+    // neighbours in the same block (eigenvalues of a block are consecutive in j)
+    auto close = [&](int q) { return q >= st && q < st + m && fabs(s.E[q] - lam) < gapmin; };
+    const bool clustered = close(j - 1) || close(j + 1);
+    double* dp = s.piv + (long long)j * 6 * n;  // this thread's six rows of n
+    double* dm = dp + n;
+    if (!clustered) {
+        // twisted factorisation of T - lam I on the block
+        double q = 1.0;
+        for (int i = 0; i < m; ++i) {
+            double qi = (s.d[st + i] - lam) - ((i > 0) ? s.e[st + i - 1] * s.e[st + i - 1] / q : 0.0);
+            if (fabs(qi) < pivmin) qi = -pivmin;
+            dp[i] = qi;
+            q = qi;
+        }
+        q = 1.0;
+        for (int i = m - 1; i >= 0; --i) {
+            double qi = (s.d[st + i] - lam) - ((i < m - 1) ? s.e[st + i] * s.e[st + i] / q : 0.0);
+            if (fabs(qi) < pivmin) qi = -pivmin;
+            dm[i] = qi;
+            q = qi;
+        }
+        int r = 0;
+        double best = 1e300;
+        for (int i = 0; i < m; ++i) {
+            const double g = dp[i] + dm[i] - (s.d[st + i] - lam);
+            if (fabs(g) < best) {
+                best = fabs(g);
+                r = i;
+            }
+        }
+        // z_r = 1; z_i = -e_i z_{i+1} / dp_i (i < r); z_i = -e_{i-1} z_{i-1} / dm_i (i > r)
+        double nrm = 1.0;
+        dp[r] = 1.0;  // dp reused for z
+        for (int i = r - 1; i >= 0; --i) {
+            const double z = -s.e[st + i] * dp[i + 1] / dp[i];
+            dp[i] = z;
+            nrm += z * z;
+        }
+        double zp = 1.0;
+        for (int i = r + 1; i < m; ++i) {
+            const double z = -s.e[st + i - 1] * zp / dm[i];
+            dm[i] = z;
+            zp = z;
+            nrm += z * z;
+        }
+        const double inv = 1.0 / sqrt(nrm);
+        for (int i = 0; i < m; ++i) {
+            const double z = (i <= r) ? dp[i] : dm[i];
+            s.U[(long long)(st + i) * n + j] = c_make(z * inv, 0.0);
+        }
+        if (!isfinite(inv)) atomicOr(a.status, kStatNonFinite);
+        return;
+    }
+    // a cluster (a run of eigenvalues of one block with consecutive gaps below
+    // gapmin): its first member does all of it, in its own six rows
+    if (close(j - 1)) return;
+    int last = j;
+    while (last + 1 < st + m && s.E[last + 1] - s.E[last] < gapmin) ++last;
+    double* x = dp;
+    double* u0 = dm;
+    double* u1 = dp + 2 * n;
+    double* u2 = dp + 3 * n;
+    double* l = dp + 4 * n;
+    int* pv = reinterpret_cast<int*>(dp + 5 * n);
+    const double floor_solve = 2.220446049250313e-16 * fmax(span, 1e-300);
+    for (int c = j; c <= last; ++c) {
+        const double lc = s.E[c] + (double)(c - j) * 2.220446049250313e-16 * span;  // separate the shifts
+        for (int i = 0; i < m; ++i) x[i] = big_start(c, i);
+        for (int itr = 0; itr < 3; ++itr) {
+            big_tri_solve(s.d, s.e, st, m, lc, floor_solve, x, u0, u1, u2, l, pv);
+            // orthogonalise against the cluster's earlier members (modified Gram-Schmidt)
+            for (int c2 = j; c2 < c; ++c2) {
+                double dot = 0.0;
+                for (int i = 0; i < m; ++i) dot += s.U[(long long)(st + i) * n + c2].x * x[i];
+                for (int i = 0; i < m; ++i) x[i] -= dot * s.U[(long long)(st + i) * n + c2].x;
+            }
+            double nrm = 0.0;
+            for (int i = 0; i < m; ++i) nrm += x[i] * x[i];
+            const double inv = 1.0 / sqrt(nrm);
+            for (int i = 0; i < m; ++i) x[i] *= inv;
+        }
+        for (int i = 0; i < m; ++i) s.U[(long long)(st + i) * n + c] = c_make(x[i], 0.0);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// step 2d: T factors of the reflector blocks (kBigB reflectors per block,
+// columns k0 .. k0+kBigB-1 of V): TF = upper triangular with TF_jj = tau_j,
+// TF(0:j, j) = -tau_j TF(0:j, 0:j) (V(:, 0:j)^+ v_j)  (compact WY, Schreiber and
+// Van Loan 1989).  grid: (blocks, items), 256 threads.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_big_tfac(BigLaunch a) {
+    __shared__ double2 C[kBigB][kBigB + 1];
+    __shared__ double2 T[kBigB][kBigB + 1];
+    const int blk = blockIdx.x, b = blockIdx.y;
+    const int n = a.n;
+    const BigSlice s = big_slice(a, b);
+    const int k0 = blk * kBigB;
+    const int bs = min(kBigB, n - 1 - k0);
+    for (int e = threadIdx.x; e < kBigB * kBigB; e += blockDim.x) {
+        const int i = e / kBigB, j = e - (e / kBigB) * kBigB;
+        double2 acc = c_make(0.0, 0.0);
+        if (i < j && j < bs)
+            for (int r = k0 + j + 1; r < n; ++r)
+                acc = c_fmac(s.V[(long long)r * n + k0 + i], s.V[(long long)r * n + k0 + j], acc);
+        C[i][j] = acc;
+        T[i][j] = c_make(0.0, 0.0);
+    }
+    __syncthreads();
+    for (int j = 0; j < bs; ++j) {
+        const double2 tj = s.tau[k0 + j];
+        const int i = threadIdx.x;
+        if (i < j) {
+            double2 acc = c_make(0.0, 0.0);
+            for (int l = i; l < j; ++l) acc = c_fma(T[i][l], C[l][j], acc);
+            T[i][j] = c_mul(c_make(-tj.x, -tj.y), acc);
+        } else if (i == j) {
+            T[j][j] = tj;
+        }
+        __syncthreads();
+    }
+    double2* out = s.TF + (long long)blk * kBigB * kBigB;
+    for (int e = threadIdx.x; e < kBigB * kBigB; e += blockDim.x) out[e] = T[e / kBigB][e % kBigB];
+}
+
+// ---------------------------------------------------------------------------
+// batched complex product C = alpha op(A) op(B) + beta C (alpha = +-1, beta = 0 or 1)
+// on FP64 MFMA: one 64 x 64 tile of C per 256-thread workgroup (grid: (N tiles,
+// M tiles, items)), panels of 16 inner indices staged through LDS with coalesced
+// reads, each wavefront a 32 x 32 block as 2 x 2 tiles of v_mfma_f64_16x16x4 (four
+// real products per complex one).  op: 0 = as stored (row-major, leading dimension
+// ld), 1 = conjugate transpose.  The operands are addressed as base + item * stride.
+// ---------------------------------------------------------------------------
+template <int OPA, int OPB>
+__global__ __launch_bounds__(256) void k_big_gemm(BigGemm g) {
+    constexpr int KT = 16, LDA = KT + 1, LDB = 64 + 1;
+    __shared__ double2 As[64 * LDA];
+    __shared__ double2 Bs[KT * LDB];
+    const int b = blockIdx.z;
+    const double2* A = g.A + (long long)b * g.sa;
+    const double2* B = g.B + (long long)b * g.sb;
+    double2* C = g.C + (long long)b * g.sc;
+    const int i0 = 64 * blockIdx.y, j0 = 64 * blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int gq = lane >> 4, c = lane & 15, wr = w >> 1, wc = w & 1;
+    const v4d zero = {0.0, 0.0, 0.0, 0.0};
+    v4d cr[2][2], ci[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+            cr[x][y] = zero;
+            ci[x][y] = zero;
+        }
+    for (int kb = 0; kb < g.K; kb += KT) {
+        __syncthreads();
+        for (int e = tid; e < 64 * KT; e += 256) {
+            // A panel: op(A)(i, k), rows i0.., inner kb..
+            {
+                const int ii = OPA ? (e & 63) : (e / KT), kk = OPA ? (e >> 6) : (e - (e / KT) * KT);
+                const int gi = i0 + ii, gk = kb + kk;
+                double2 v = c_make(0.0, 0.0);
+                if (gi < g.M && gk < g.K) v = OPA ? c_conj(A[(long long)gk * g.lda + gi]) : A[(long long)gi * g.lda + gk];
+                As[ii * LDA + kk] = v;
+            }
+            // B panel: op(B)(k, j)
+            {
+                const int jj = OPB ? (e / KT) : (e & 63), kk = OPB ? (e - (e / KT) * KT) : (e >> 6);
+                const int gj = j0 + jj, gk = kb + kk;
+                double2 v = c_make(0.0, 0.0);
+                if (gj < g.N && gk < g.K) v = OPB ? c_conj(B[(long long)gj * g.ldb + gk]) : B[(long long)gk * g.ldb + gj];
+                Bs[kk * LDB + jj] = v;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k4 = 0; k4 < KT / 4; ++k4) {
+            double2 av[2], bv[2];
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                av[t] = As[(32 * wr + 16 * t + c) * LDA + 4 * k4 + gq];
+                bv[t] = Bs[(4 * k4 + gq) * LDB + 32 * wc + 16 * t + c];
+            }
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y) {
+                    cr[x][y] = mfma(av[x].x, bv[y].x, cr[x][y]);
+                    ci[x][y] = mfma(av[x].x, bv[y].y, ci[x][y]);
+                    cr[x][y] = mfma(-av[x].y, bv[y].y, cr[x][y]);
+                    ci[x][y] = mfma(av[x].y, bv[y].x, ci[x][y]);
+                }
+        }
+    }
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = i0 + 32 * wr + 16 * x + gq + 4 * q, col = j0 + 32 * wc + 16 * y + c;
+                if (row < g.M && col < g.N) {
+                    double2& o = C[(long long)row * g.ldc + col];
+                    const double2 v = c_make(g.alpha * cr[x][y][q], g.alpha * ci[x][y][q]);
+                    o = g.beta ? c_add(o, v) : v;
+                }
+            }
+}
+
+// ---------------------------------------------------------------------------
+// step 4: Omega_n = -2 sum_{m != n} Im(A_nm B_mn) g(E_n - E_m) (B_mn = conj(B_nm))
+// from A in VX and B in VY, then sum_n f(E_n; E_F[j]) Omega_n into the item's slot.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBigMaxN) void k_big_curv(BigLaunch a) {
+    __shared__ double Om[kBigMaxN], Ev[kBigMaxN];
+    const int b = blockIdx.x;
+    const BlockItem it = a.tb.blocks[a.item_begin + b];
+    const ModelDev md = a.tb.models[it.model];
+    const int n = a.n;
+    const BigSlice s = big_slice(a, b);
+    const double eta2 = a.eta * a.eta;
+    const int t = threadIdx.x;
+    if (t < n) {
+        const double en = s.E[t];
+        double om = 0.0;
+        for (int m = 0; m < n; ++m) {
+            if (m == t) continue;
+            const double2 x = s.VX[(long long)t * n + m], y = s.VY[(long long)t * n + m];
+            const double de = en - s.E[m];
+            const double den = de * de + eta2;
+            // Im(A_nm conj(B_nm))
+            if (den > 0.0) om += (x.y * y.x - x.x * y.y) / den;
+        }
+        Om[t] = -2.0 * om;
+        Ev[t] = en;
+    }
+    __syncthreads();
+    double* part = a.partial + (long long)it.slot * a.nF;
+    const double* ef = a.e_fermi + md.f_off;
+    const double ikT = (a.kT > 0.0) ? 1.0 / a.kT : 0.0;
+    for (int j = t; j < a.nF; j += blockDim.x) {
+        double sum = 0.0;
+        for (int m = 0; m < n; ++m) sum += occupation_ikt(Ev[m], ef[j], a.kT, ikT) * Om[m];
+        if (!isfinite(sum)) atomicOr(a.status, kStatNonFinite);
+        part[j] = sum;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side: the pipeline for `count` items of one model of size n
+// ---------------------------------------------------------------------------
+static hipError_t gemm(int opa, int opb, const BigGemm& g, int items, hipStream_t s) {
+    dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, items);
+    if (opa == 0 && opb == 0) hipLaunchKernelGGL((k_big_gemm<0, 0>), grid, dim3(256), 0, s, g);
+    else if (opa == 1 && opb == 0) hipLaunchKernelGGL((k_big_gemm<1, 0>), grid, dim3(256), 0, s, g);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_big_forward(const BigLaunch& L, hipStream_t s) {
+    if (L.count <= 0) return hipSuccess;
+    if (L.n < 2 || L.n > kBigMaxN) return hipErrorInvalidValue;
+    const int n = L.n;
+    const long long nn = (long long)n * n;
+    const long long pk = L.per_k;
+    const BigLayout Y = big_layout(n);
+    if (pk < Y.per_k) return hipErrorInvalidValue;
+    hipError_t e;
+    hipLaunchKernelGGL(k_big_build, dim3((unsigned)((nn + 255) / 256 < 64 ? (nn + 255) / 256 : 64), L.count),
+                       dim3(256), 0, s, L);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_big_tridiag, dim3(L.count), dim3(1024), 0, s, L);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_big_eig, dim3(L.count), dim3(kBigMaxN), 0, s, L);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_big_vec, dim3(L.count), dim3(kBigMaxN), 0, s, L);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int nb = (n - 1 + kBigB - 1) / kBigB;  // reflector blocks (n - 1 reflectors)
+    hipLaunchKernelGGL(k_big_tfac, dim3(nb, L.count), dim3(256), 0, s, L);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // the matrices of the first slice (the products step by per_k from item to item)
+    double2* base = reinterpret_cast<double2*>(L.scratch);
+    double2* VX = base + Y.VX;
+    double2* VY = base + Y.VY;
+    double2* U = base + Y.U;
+    double2* X = base + Y.X;
+    double2* V = base + Y.V;
+    double2* W = base + Y.W;
+    double2* W2 = base + Y.W2;
+    double2* TF = base + Y.TF;
+    // back-transformation: Z (in U) <- Q_b Z for the blocks from last to first
+    for (int blk = nb - 1; blk >= 0; --blk) {
+        const int k0 = blk * kBigB;
+        const int bs = (n - 1 - k0) < kBigB ? (n - 1 - k0) : kBigB;
+        BigGemm g{};
+        // W = V_b^+ Z  (bs x n)
+        g.A = V + k0; g.lda = n; g.sa = pk;
+        g.B = U; g.ldb = n; g.sb = pk;
+        g.C = W; g.ldc = n; g.sc = pk;
+        g.M = bs; g.N = n; g.K = n; g.alpha = 1.0; g.beta = 0;
+        if ((e = gemm(1, 0, g, L.count, s)) != hipSuccess) return e;
+        // W2 = T W  (bs x n)
+        g.A = TF + (long long)blk * kBigB * kBigB; g.lda = kBigB; g.sa = pk;
+        g.B = W; g.ldb = n; g.sb = pk;
+        g.C = W2; g.ldc = n; g.sc = pk;
+        g.M = bs; g.N = n; g.K = bs; g.alpha = 1.0; g.beta = 0;
+        if ((e = gemm(0, 0, g, L.count, s)) != hipSuccess) return e;
+        // Z -= V_b W2  (n x n)
+        g.A = V + k0; g.lda = n; g.sa = pk;
+        g.B = W2; g.ldb = n; g.sb = pk;
+        g.C = U; g.ldc = n; g.sc = pk;
+        g.M = n; g.N = n; g.K = bs; g.alpha = -1.0; g.beta = 1;
+        if ((e = gemm(0, 0, g, L.count, s)) != hipSuccess) return e;
+    }
+    // rotations: X = v U, then v' = U^+ X into the velocity's own buffer
+    for (double2* Vel : {VX, VY}) {
+        BigGemm g{};
+        g.A = Vel; g.lda = n; g.sa = pk;
+        g.B = U; g.ldb = n; g.sb = pk;
+        g.C = X; g.ldc = n; g.sc = pk;
+        g.M = n; g.N = n; g.K = n; g.alpha = 1.0; g.beta = 0;
+        if ((e = gemm(0, 0, g, L.count, s)) != hipSuccess) return e;
+        g.A = U; g.lda = n; g.sa = pk;
+        g.B = X; g.ldb = n; g.sb = pk;
+        g.C = Vel; g.ldc = n; g.sc = pk;
+        if ((e = gemm(1, 0, g, L.count, s)) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_big_curv, dim3(L.count), dim3(kBigMaxN), 0, s, L);
+    return hipGetLastError();
+}
+
+}  // namespace kubo

@@ -29,12 +29,15 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 // Size classes of the per-k kernels (forward and adjoint alike): one wavefront
 // per k-point with the matrices padded to np (n <= 32), or one workgroup per
 // k-point with the matrices in workspace scratch (n <= 64: register
-// back-transformation at two waves per SIMD; n <= 128: the LDS-staged one).
+// back-transformation at two waves per SIMD; n <= 128: the LDS-staged one), or
+// (n <= 512, forward only) the large-n pipeline, many workgroups per k-point.
 struct ClassInfo {
     int np;
     bool wave;
+    bool big;
 };
-const ClassInfo kClasses[] = {{8, true}, {16, true}, {32, true}, {64, false}, {128, false}};
+const ClassInfo kClasses[] = {{8, true, false},   {16, true, false},   {32, true, false},
+                              {64, false, false}, {128, false, false}, {512, false, true}};
 constexpr int kNumClasses = sizeof(kClasses) / sizeof(kClasses[0]);
 
 int class_of(int n) {
@@ -109,6 +112,7 @@ struct kubo_plan_s {
     size_t off_queues = 0, off_tables = 0, off_tp = 0, off_tbuf = 0, off_pbuf = 0, off_xbuf = 0, off_partial = 0,
            total = 0;
     size_t off_scratch = 0;
+    size_t off_big = 0, big_bytes = 0;  // the large-n pipeline's slices
     long long slot_elems = 0;
     int wg_groups = 512;
     int n_queues = 0;  // per-k kernel launches (forward chunks, then backward), 8 counters each
@@ -242,6 +246,7 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
         int kblock = std::min(d.grid[0], d.n_orb > 32 ? 8 : 32);
         auto ti = tile_of.find(d.n_orb);
         if (ti != tile_of.end()) kblock = std::min(d.grid[0], ti->second.k_block);
+        if (d.n_orb > 128) kblock = 1;  // the large-n pipeline: one k-point per item
         // the backward writes one set of pencil partials per k-block and sums them
         // afterwards, so it takes blocks of about 32 points, balanced over the pencil
         const int nbb = (d.grid[0] + 31) / 32;
@@ -329,7 +334,9 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
             if (!with_p) {
                 // forward: deal whole pencils round-robin into eight bins, one per XCD
                 // share of the persistent grid, so every XCD sees the same mix of models
+                // (not the large-n class: its batches take runs of one model in order)
                 for (int c = 0; c < kNumClasses; ++c) {
+                    if (kClasses[c].big) continue;
                     std::vector<BlockItem> bins[8];
                     int p = -1;
                     for (size_t i = 0; i < cls_blocks[c].size(); ++i) {
@@ -440,7 +447,8 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
     P->n_orb_total = orb_off;
     {
         int nmax = 1;
-        for (const auto& md : P->models) nmax = std::max(nmax, md.n);
+        for (const auto& md : P->models)
+            if (md.n <= 128) nmax = std::max(nmax, md.n);
         P->slot_elems = wg_slot_elems(nmax);
         // most work units of one launch (a backward item splits into units of
         // at most kUnitK k-points)
@@ -459,11 +467,24 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
         for (const kubo_plan_s::ChunkSet* cs : {&P->fwd, &P->bwd})
             for (const Chunk& c : cs->chunks)
                 for (int k = 0; k < kNumClasses; ++k)
-                    if (!kClasses[k].wave && c.cls[k].count > 0) any_wg = true;
+                    if (!kClasses[k].wave && !kClasses[k].big && c.cls[k].count > 0) any_wg = true;
         if (!any_wg) P->slot_elems = 0;
     }
     P->off_scratch = off;
     off = align_up(off + (size_t)P->wg_groups * (size_t)P->slot_elems * 16);
+    // the large-n pipeline's per-k slices: room for a batch of up to kBigBatch
+    // k-points of the largest such model, within four times the chunk cap
+    P->big_bytes = 0;
+    for (const auto& md : P->models) {
+        if (md.n <= 128) continue;
+        long long most_k = 0;
+        for (const Chunk& c : P->fwd.chunks) most_k = std::max(most_k, (long long)c.cls[kNumClasses - 1].count);
+        const size_t slice = (size_t)big_layout(md.n).per_k * 16;
+        const size_t want = slice * (size_t)std::min<long long>(most_k, kBigBatch);
+        P->big_bytes = std::max(P->big_bytes, std::max(slice, std::min(want, 4 * cap)));
+    }
+    P->off_big = off;
+    off = align_up(off + P->big_bytes);
     P->total = off;
     return KUBO_OK;
 }
@@ -478,7 +499,7 @@ kubo_status validate(const kubo_model_desc* models, int n_models, int nF, uint32
     if (n_tiles < 0 || (n_tiles > 0 && !tiles)) return KUBO_E_INVALID;
     for (int i = 0; i < n_tiles; ++i) {
         const kubo_tile& t = tiles[i];
-        if (t.n_orb < 1 || t.n_orb > kMaxOrb || t.k_block < 1 || t.reserved != 0)
+        if (t.n_orb < 1 || t.n_orb > 128 || t.k_block < 1 || t.reserved != 0)
             return KUBO_E_INVALID;
         if (t.threads != 0 && t.threads != 64 && t.threads != 256) return KUBO_E_INVALID;
         if (t.threads == 64 && t.n_orb > 32) return KUBO_E_INVALID;
@@ -507,6 +528,9 @@ kubo_status validate(const kubo_model_desc* models, int n_models, int nF, uint32
                 return KUBO_E_INVALID;
         if (d.n_orb > kMaxOrb) unsupported = true;
         else if (class_of(d.n_orb) < 0) unsupported = true;
+        // n > 128 runs the large-n pipeline, which has the forward only
+        if (d.n_orb > 128 && (!(flags & KUBO_F_FORWARD_ONLY) || (flags & KUBO_F_TENSOR)))
+            unsupported = true;
         if (xs.size() > 16) unsupported = true;
     }
     return unsupported ? KUBO_E_UNSUPPORTED : KUBO_OK;
@@ -606,7 +630,35 @@ kubo_status enqueue_forward(kubo_plan_s* P, const double* t, const double* ef, d
         for (int k = 0; k < kNumClasses; ++k) {
             if (c.cls[k].count == 0) continue;
             TimedScope ts(P, s, tensor ? 2 : 0, c.cls_kpts[k]);
-            if (kClasses[k].wave) {
+            if (kClasses[k].big) {
+                // runs of items of one model, at most a batch's worth at a time
+                const BlockItem* items = P->fwd.blocks.data();
+                for (int i = c.cls[k].begin; i < c.cls[k].begin + c.cls[k].count;) {
+                    const int m = items[i].model;
+                    const int n = P->models[m].n;
+                    const long long per_k = big_layout(n).per_k;
+                    const int batch = (int)std::max<long long>(
+                        1, std::min<long long>(kBigBatch, (long long)(P->big_bytes / 16) / per_k));
+                    int j = i + 1;
+                    while (j < c.cls[k].begin + c.cls[k].count && j - i < batch && items[j].model == m) ++j;
+                    BigLaunch L{};
+                    L.tb = tb;
+                    L.tbuf = tbuf;
+                    L.e_fermi = ef;
+                    L.partial = partial;
+                    L.status = status;
+                    L.scratch = reinterpret_cast<double*>(ws + P->off_big);
+                    L.per_k = per_k;
+                    L.eta = eta;
+                    L.kT = kT;
+                    L.nF = P->nF;
+                    L.n = n;
+                    L.item_begin = i;
+                    L.count = j - i;
+                    HIP_TRY(launch_big_forward(L, s));
+                    i = j;
+                }
+            } else if (kClasses[k].wave) {
                 FwdLaunch L;
                 L.tb = tb;
                 L.tbuf = tbuf;

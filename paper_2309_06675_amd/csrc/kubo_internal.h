@@ -5,7 +5,7 @@
 
 namespace kubo {
 
-constexpr int kMaxOrb = 128;
+constexpr int kMaxOrb = 512;
 constexpr int kMaxFermi = 4096;
 constexpr int kMaxSweeps = 30;
 

@@ -70,6 +70,66 @@ struct GfLaunch {
 };
 hipError_t launch_gf(const GfLaunch& L, hipStream_t s);
 
+// The large-n path (kBigMinN < n <= kBigMaxN): a batch of `count` items (one
+// k-point each) of one model of size n, each with a workspace slice of per_k
+// complex elements laid out by big_layout.
+constexpr int kBigMaxN = 512;
+constexpr int kBigB = 32;          // reflectors per compact-WY block
+constexpr double kBigGap = 1e-3;   // relative gap below which eigenvalues form a cluster
+constexpr int kBigBatch = 256;     // most k-points of one pipeline pass
+struct BigLayout {
+    long long H, VX, VY, U, X, V, W, W2, TF, tau;  // complex offsets
+    long long d, e, E, piv, blk;                   // double offsets (from the start of the slice)
+    long long per_k;                               // complex elements per k-point
+};
+__host__ __device__ inline BigLayout big_layout(int n) {
+    const long long nn = (long long)n * n;
+    const long long nb = (n + kBigB - 1) / kBigB;
+    BigLayout L;
+    L.H = 0;
+    L.VX = L.H + nn;
+    L.VY = L.VX + nn;
+    L.U = L.VY + nn;
+    L.X = L.U + nn;
+    L.V = L.X + nn;
+    L.W = L.V + nn;
+    L.W2 = L.W + (long long)kBigB * n;
+    L.TF = L.W2 + (long long)kBigB * n;
+    L.tau = L.TF + nb * kBigB * kBigB;
+    const long long dbase = 2 * (L.tau + n);  // doubles
+    L.d = dbase;
+    L.e = L.d + n;
+    L.E = L.e + n;
+    L.piv = L.E + n;          // 6 n doubles per eigenvalue thread
+    L.blk = L.piv + 6 * nn;   // n ints (stored in n doubles)
+    L.per_k = (L.blk + n + 1) / 2 + 1;
+    return L;
+}
+struct BigLaunch {
+    Tables tb;
+    const double* tbuf;
+    const double* e_fermi;
+    double* partial;
+    unsigned* status;
+    double* scratch;  // count slices of per_k complex elements
+    long long per_k;
+    double eta, kT;
+    int nF;
+    int n;
+    int item_begin, count;
+};
+struct BigGemm {
+    const double2* A;
+    const double2* B;
+    double2* C;
+    long long sa, sb, sc;  // batch strides (complex elements)
+    int lda, ldb, ldc;
+    int M, N, K;
+    double alpha;
+    int beta;
+};
+hipError_t launch_big_forward(const BigLaunch& L, hipStream_t s);
+
 long long wg_slot_elems(int nmax);
 // np: the size class (64: n <= 64, 128: n <= 128)
 hipError_t launch_forward_wg(const WgLaunch& L, int np, hipStream_t s);

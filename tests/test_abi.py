@@ -96,8 +96,19 @@ def test_plan_rejects_bad_tile():
 
 
 def test_plan_unsupported_size():
-    d, keep = _desc(n=200)
+    d, keep = _desc(n=600)
+    assert _plan_status([d], flags=kubo.KUBO_F_FORWARD_ONLY)[0] == kubo.KUBO_E_UNSUPPORTED
+
+
+def test_large_n_plans_are_forward_only():
+    """128 < n <= 512 runs the large-n pipeline: the plan must be forward-only and not a
+    tensor plan; its workspace holds the pipeline's per-k slices."""
+    d, keep = _desc(n=200, grid=(3, 2, 2))
     assert _plan_status([d])[0] == kubo.KUBO_E_UNSUPPORTED
+    assert _plan_status([d], flags=kubo.KUBO_F_FORWARD_ONLY | kubo.KUBO_F_TENSOR)[0] == \
+        kubo.KUBO_E_UNSUPPORTED
+    st, ws = _plan_status([d], flags=kubo.KUBO_F_FORWARD_ONLY)
+    assert st == kubo.KUBO_OK and ws > 12 * 200 * 200 * 16
 
 
 def test_null_plan_pointer():
