@@ -322,6 +322,40 @@ def measure_gf(reps: int = 3, n_fermi: int = 8, n_omega: int = 16, gamma: float 
             "sigma_checksum": float(sig.sum().item())}
 
 
+def measure_large_n(reps: int = 3, n: int = 256, grid=(16, 16, 16), n_fermi: int = 16):
+    """The large-n path (128 < n <= 512: many workgroups per k-point): a random n = 256 model
+    on R in {-1..1}^3 (27 lattice vectors), a 16^3 grid, 16 Fermi levels over [-3, 3],
+    eta = 1e-3, kT = 0.01; median of `reps` forward passes."""
+    import torch
+
+    from paper_2309_06675_amd import kubo, synth
+
+    m = synth.random_model(n, 1, 1.0, 4000 + n)
+    nk = grid[0] * grid[1] * grid[2]
+    ef = np.linspace(-3.0, 3.0, n_fermi).reshape(1, n_fermi)
+    dev = "cuda:0"
+    stream = torch.cuda.current_stream(dev)
+    plan = kubo.Plan([m], grid=grid, n_fermi=n_fermi,
+                     flags=kubo.KUBO_F_FORWARD_ONLY | kubo.KUBO_F_TIMING, device=dev)
+    t = kubo.to_device_t([m], dev)
+    efd = torch.from_numpy(ef).to(dev)
+    sig = torch.empty(1, n_fermi, dtype=torch.float64, device=dev)
+    plan.forward(t, efd, 1e-3, 0.01, out=sig)
+    torch.cuda.synchronize()
+    ms, alls = _timed_median(lambda: plan.forward(t, efd, 1e-3, 0.01, out=sig), reps, stream)
+    st = plan.device_status()
+    if st != kubo.KUBO_OK:
+        raise SystemExit(f"large-n device status: {kubo.kubo_status_string(st)}")
+    fpk = forward_flops_per_k(m.n, m.n_R, n_rx(m), grid[0], n_fermi, True)
+    print(f"large n={n} {ms:.1f} ms", file=sys.stderr, flush=True)
+    return {"workload": f"n{n}_R27_k16^3_F{n_fermi}_kT0.01", "k_points": nk, "reps": reps,
+            "ms_median": ms, "ms_all": alls, "k_points_per_s": nk / (ms / 1e3),
+            "flops_per_k": fpk,
+            "tflops": fpk * nk / (ms / 1e3) / 1e12,
+            "frac": fpk * nk / (ms / 1e3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
+            "sigma_checksum": float(sig.sum().item())}
+
+
 def measure_large(adjoint: bool = True, parts: int = 16):
     """The n_orb = 128 workload over its whole 128^3 grid (forward at eta = 1e-3, adjoint at
     eta = 1e-2), enqueued as `parts` consecutive k-slabs (slabs add up exactly; each slab
@@ -493,9 +527,11 @@ def main(argv=None):
                     help="only run two elementwise FP64 kernels on MB megabytes (counter calibration)")
     ap.add_argument("--large", action="store_true",
                     help="only run the n_orb = 128 workload over its full grid and print it")
+    ap.add_argument("--large-n-reps", type=int, default=3,
+                    help="timed passes (median) of the n = 256 large-n workload (0 skips)")
     ap.add_argument("--gf-reps", type=int, default=3,
                     help="timed passes (median) of the Green's-function form (0 skips)")
-    ap.add_argument("--legs", default="forward,adjoint,n128,batched,gf,cpu",
+    ap.add_argument("--legs", default="forward,adjoint,n128,batched,gf,large_n,cpu",
                     help="comma-separated legs to run (forward is always run; for profiling)")
     args = ap.parse_args(argv)
     legs = set(args.legs.split(","))
@@ -619,6 +655,8 @@ def main(argv=None):
         out["n128_slab"] = measure_cfg4_slab(reps=args.large_reps)
     if args.gf_reps > 0 and "gf" in legs:
         out["gf"] = measure_gf(args.gf_reps)
+    if args.large_n_reps > 0 and "large_n" in legs:
+        out["large_n"] = measure_large_n(args.large_n_reps)
     if args.batched_steps > 0 and "batched" in legs:
         out["batched"] = measure_batched(args.batched_steps, 1)
     if args.cpu_sample > 0 and "cpu" in legs:

@@ -119,7 +119,7 @@ __global__ __launch_bounds__(256) void k_big_build(BigLaunch a) {
 // the diagonal to d and the off-diagonal to e.  One workgroup per k-point.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_big_tridiag(BigLaunch a) {
-    __shared__ double2 v[kBigMaxN], w[kBigMaxN], p[kBigMaxN];
+    __shared__ double2 v[kBigMaxN], w[kBigMaxN], p[kBigMaxN], pp[4][kBigMaxN];
     __shared__ double red[16];
     __shared__ double2 sh_tau, sh_scal;
     __shared__ double sh_beta;
@@ -171,13 +171,20 @@ __global__ __launch_bounds__(1024) void k_big_tridiag(BigLaunch a) {
         __syncthreads();
         if (tau.x == 0.0 && tau.y == 0.0) continue;
         // p = A v over the trailing block; A Hermitian: p_i = sum_j conj(A_ji) v_j, read
-        // along rows j (consecutive threads, consecutive columns i)
-        for (int i = tid; i < m; i += nt) {
-            double2 acc = c_make(0.0, 0.0);
-            for (int j = 0; j < m; ++j)
-                acc = c_fmac(A[(long long)(k + 1 + j) * n + k + 1 + i], v[j], acc);
-            p[i] = acc;
+        // along rows j (consecutive threads, consecutive columns i); four threads per
+        // column i take every fourth j, then the four partial sums are added
+        {
+            const int q = tid >> 8, i0 = tid & 255;
+            for (int i = i0; i < m; i += 256) {
+                double2 acc = c_make(0.0, 0.0);
+                for (int j = q; j < m; j += 4)
+                    acc = c_fmac(A[(long long)(k + 1 + j) * n + k + 1 + i], v[j], acc);
+                pp[q][i] = acc;
+            }
         }
+        __syncthreads();
+        for (int i = tid; i < m; i += nt)
+            p[i] = c_add(c_add(pp[0][i], pp[1][i]), c_add(pp[2][i], pp[3][i]));
         __syncthreads();
         double mu = 0.0;
         for (int i = tid; i < m; i += nt) mu += v[i].x * p[i].x + v[i].y * p[i].y;
@@ -185,11 +192,12 @@ __global__ __launch_bounds__(1024) void k_big_tridiag(BigLaunch a) {
         const double t2 = 0.5 * (tau.x * tau.x + tau.y * tau.y) * mu;
         for (int i = tid; i < m; i += nt) w[i] = c_sub(c_mul(tau, p[i]), c_scale(t2, v[i]));
         __syncthreads();
-        // A <- A - v w^+ - w v^+ on the trailing block
-        for (long long e = tid; e < (long long)m * m; e += nt) {
-            const int i = (int)(e / m), j = (int)(e - (long long)(e / m) * m);
-            double2& aij = A[(long long)(k + 1 + i) * n + k + 1 + j];
-            aij = c_rank2c(aij, v[i], w[j], w[i], v[j]);
+        // A <- A - v w^+ - w v^+ on the trailing block (32 rows at a time, 32
+        // consecutive columns per row)
+        for (int i = tid >> 5; i < m; i += nt >> 5) {
+            double2* row = A + (long long)(k + 1 + i) * n + k + 1;
+            const double2 vi = v[i], wi = w[i];
+            for (int j = tid & 31; j < m; j += 32) row[j] = c_rank2c(row[j], vi, w[j], wi, v[j]);
         }
         __syncthreads();
     }
@@ -257,7 +265,9 @@ __global__ __launch_bounds__(kBigMaxN) void k_big_eig(BigLaunch a) {
         double q = 1.0;
         for (int i = st; i < st + m; ++i) {
             const double e2 = (i > st) ? s.e[i - 1] * s.e[i - 1] : 0.0;
-            double qi = (s.d[i] - x) - ((i > st) ? e2 / q : 0.0);
+            double r = __builtin_amdgcn_rcp(q);
+            r = fma(r, fma(-q, r, 1.0), r);
+            double qi = fma(-e2, r, s.d[i] - x);
             if (fabs(qi) < pivmin) qi = -pivmin;
             cnt += (qi < 0.0) ? 1 : 0;
             q = qi;

@@ -75,7 +75,7 @@ hipError_t launch_gf(const GfLaunch& L, hipStream_t s);
 // complex elements laid out by big_layout.
 constexpr int kBigMaxN = 512;
 constexpr int kBigB = 32;          // reflectors per compact-WY block
-constexpr double kBigGap = 1e-3;   // relative gap below which eigenvalues form a cluster
+constexpr double kBigGap = 1e-5;   // relative gap below which eigenvalues form a cluster
 constexpr int kBigBatch = 256;     // most k-points of one pipeline pass
 struct BigLayout {
     long long H, VX, VY, U, X, V, W, W2, TF, tau;  // complex offsets
