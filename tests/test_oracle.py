@@ -23,7 +23,7 @@ def _herm(n, seed):
     return 0.5 * (x + x.conj().T)
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 7, 16, 33])
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 16, 33, 150])
 def test_jacobi_matches_lapack(oracle, n):
     H = _herm(n, 11 + n)
     E, U, sw = oracle.eigh(H)
