@@ -117,94 +117,153 @@ __global__ __launch_bounds__(256) void k_big_build(BigLaunch a) {
 // tridiagonal T = Q^+ H Q, Q = H_0 ... H_{n-2}, H_k = I - tau_k v_k v_k^+ with
 // v_k[k+1] = 1.  The reflectors go to V (column k, zero elsewhere), tau to tau,
 // the diagonal to d and the off-diagonal to e.  One workgroup per k-point.
+// The trailing matrix is bandwidth-bound, so step k's rank-2 update and step
+// k+1's product p = A v share one pass over it: column k+1 of the updated
+// matrix is formed first (from the old values and step k's v, w), giving
+// v_{k+1}; then every element is updated, written back and, for the rows and
+// columns of step k+1, accumulated into p_{k+1} (p_i = sum_j conj(A_ji) v_j, four
+// threads per column i reading rows j).
 // ---------------------------------------------------------------------------
+namespace {
+
+// reflector of x (m entries, x[0] the first) into v (v[0] = 1); returns tau and
+// writes beta (the new subdiagonal entry); thread 0 decides, all threads scale.
+__device__ __forceinline__ double2 big_reflector(double2* v, int m, double xn2, double& beta,
+                                                 double2* sh, double* shb) {
+    if (threadIdx.x == 0) {
+        const double2 alpha = v[0];
+        double bt;
+        double2 tau, scal;
+        if (xn2 == 0.0 && alpha.y == 0.0) {
+            bt = alpha.x;
+            tau = c_make(0.0, 0.0);
+            scal = c_make(0.0, 0.0);
+        } else {
+            const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn2);
+            bt = -copysign(nrm, alpha.x);
+            tau = c_make((bt - alpha.x) / bt, -alpha.y / bt);
+            const double ar = alpha.x - bt, ai = alpha.y;
+            const double den = 1.0 / (ar * ar + ai * ai);
+            scal = c_make(ar * den, -ai * den);
+        }
+        sh[0] = tau;
+        sh[1] = scal;
+        *shb = bt;
+    }
+    __syncthreads();
+    const double2 scal = sh[1];
+    for (int i = threadIdx.x; i < m; i += blockDim.x)
+        if (i > 0) v[i] = c_mul(v[i], scal);
+    if (threadIdx.x == 0) v[0] = c_make(1.0, 0.0);
+    beta = *shb;
+    const double2 tau = sh[0];
+    __syncthreads();
+    return tau;
+}
+
+}  // namespace
+
 __global__ __launch_bounds__(1024) void k_big_tridiag(BigLaunch a) {
-    __shared__ double2 v[kBigMaxN], w[kBigMaxN], p[kBigMaxN], pp[4][kBigMaxN];
+    __shared__ double2 vb[2][kBigMaxN], w[kBigMaxN], p[kBigMaxN], pp[4][kBigMaxN];
     __shared__ double red[16];
-    __shared__ double2 sh_tau, sh_scal;
-    __shared__ double sh_beta;
+    __shared__ double2 sh[2];
+    __shared__ double shb;
     const int b = blockIdx.x;
     const int n = a.n;
     const BigSlice s = big_slice(a, b);
     double2* A = s.H;
     const int tid = threadIdx.x, nt = blockDim.x;
-    for (int k = 0; k < n - 1; ++k) {
-        // column k below the diagonal
-        const int m = n - k - 1;  // rows k+1 .. n-1
+    const int q4 = tid >> 8, c0 = tid & 255;  // four threads per column
+    double2 tau_cur;  // tau of the current step, in every thread
+    // step 0: reflector of column 0 and p_0 = A v_0 (a plain pass)
+    {
+        const int m = n - 1;
+        double2* v = vb[0];
         double xn2 = 0.0;
         for (int i = tid; i < m; i += nt) {
-            const double2 x = A[(long long)(k + 1 + i) * n + k];
+            const double2 x = A[(long long)(1 + i) * n];
             v[i] = x;
             if (i > 0) xn2 += x.x * x.x + x.y * x.y;
         }
-        xn2 = block_sum(xn2, red);  // (contains barriers: v is visible after it)
+        xn2 = block_sum(xn2, red);
+        double beta;
+        const double2 tau = big_reflector(v, m, xn2, beta, sh, &shb);
+        tau_cur = tau;
         if (tid == 0) {
-            const double2 alpha = v[0];
-            double beta;
-            double2 tau, scal;
-            if (xn2 == 0.0 && alpha.y == 0.0) {
-                beta = alpha.x;
-                tau = c_make(0.0, 0.0);
-                scal = c_make(0.0, 0.0);
-            } else {
-                const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn2);
-                beta = -copysign(nrm, alpha.x);
-                tau = c_make((beta - alpha.x) / beta, -alpha.y / beta);
-                const double ar = alpha.x - beta, ai = alpha.y;
-                const double den = 1.0 / (ar * ar + ai * ai);
-                scal = c_make(ar * den, -ai * den);
-            }
-            sh_beta = beta;
-            sh_tau = tau;
-            sh_scal = scal;
-            s.d[k] = A[(long long)k * n + k].x;
-            s.e[k] = beta;
-            s.tau[k] = tau;
+            s.d[0] = A[0].x;
+            s.e[0] = beta;
+            s.tau[0] = tau;
+        }
+        for (int i = tid; i < m; i += nt) s.V[(long long)(1 + i) * n] = v[i];
+        for (int i = c0; i < m; i += 256) {
+            double2 acc = c_make(0.0, 0.0);
+            for (int j = q4; j < m; j += 4) acc = c_fmac(A[(long long)(1 + j) * n + 1 + i], v[j], acc);
+            pp[q4][i] = acc;
         }
         __syncthreads();
-        const double2 tau = sh_tau, scal = sh_scal;
-        for (int i = tid; i < m; i += nt) {
-            const double2 vi = (i == 0) ? c_make(1.0, 0.0) : c_mul(v[i], scal);
-            v[i] = vi;
-            s.V[(long long)(k + 1 + i) * n + k] = vi;
-        }
+        for (int i = tid; i < m; i += nt) p[i] = c_add(c_add(pp[0][i], pp[1][i]), c_add(pp[2][i], pp[3][i]));
         __syncthreads();
-        if (tau.x == 0.0 && tau.y == 0.0) continue;
-        // p = A v over the trailing block; A Hermitian: p_i = sum_j conj(A_ji) v_j, read
-        // along rows j (consecutive threads, consecutive columns i); four threads per
-        // column i take every fourth j, then the four partial sums are added
-        {
-            const int q = tid >> 8, i0 = tid & 255;
-            for (int i = i0; i < m; i += 256) {
-                double2 acc = c_make(0.0, 0.0);
-                for (int j = q; j < m; j += 4)
-                    acc = c_fmac(A[(long long)(k + 1 + j) * n + k + 1 + i], v[j], acc);
-                pp[q][i] = acc;
-            }
-        }
-        __syncthreads();
-        for (int i = tid; i < m; i += nt)
-            p[i] = c_add(c_add(pp[0][i], pp[1][i]), c_add(pp[2][i], pp[3][i]));
-        __syncthreads();
+    }
+    for (int k = 0; k < n - 1; ++k) {
+        const int m = n - k - 1;  // step k works on rows and columns k+1 .. n-1
+        double2* v = vb[k & 1];
+        double2* vn = vb[(k + 1) & 1];
+        const double2 tau = tau_cur;
+        // w = tau p - (|tau|^2 (v^+ p) / 2) v (zero when tau = 0: then nothing changes)
         double mu = 0.0;
         for (int i = tid; i < m; i += nt) mu += v[i].x * p[i].x + v[i].y * p[i].y;
         mu = block_sum(mu, red);
         const double t2 = 0.5 * (tau.x * tau.x + tau.y * tau.y) * mu;
         for (int i = tid; i < m; i += nt) w[i] = c_sub(c_mul(tau, p[i]), c_scale(t2, v[i]));
         __syncthreads();
-        // A <- A - v w^+ - w v^+ on the trailing block (32 rows at a time, 32
-        // consecutive columns per row)
-        for (int i = tid >> 5; i < m; i += nt >> 5) {
-            double2* row = A + (long long)(k + 1 + i) * n + k + 1;
+        if (m == 1) {  // the last diagonal entry
+            if (tid == 0) {
+                const double2 a11 = c_rank2c(A[(long long)(n - 1) * n + n - 1], v[0], w[0], w[0], v[0]);
+                s.d[n - 1] = a11.x;
+                s.e[n - 1] = 0.0;
+                s.tau[n - 1] = c_make(0.0, 0.0);
+            }
+            break;
+        }
+        // column k+1 of the updated matrix below its diagonal (rows k+2 ..): x_i, and
+        // the diagonal entry d_{k+1}
+        const int mn = m - 1;
+        double xn2 = 0.0;
+        for (int i = tid; i < mn; i += nt) {
+            const double2 x = c_rank2c(A[(long long)(k + 2 + i) * n + k + 1], v[1 + i], w[0], w[1 + i], v[0]);
+            vn[i] = x;
+            if (i > 0) xn2 += x.x * x.x + x.y * x.y;
+        }
+        xn2 = block_sum(xn2, red);
+        double beta;
+        const double2 taun = big_reflector(vn, mn, xn2, beta, sh, &shb);
+        tau_cur = taun;
+        if (tid == 0) {
+            s.d[k + 1] = c_rank2c(A[(long long)(k + 1) * n + k + 1], v[0], w[0], w[0], v[0]).x;
+            s.e[k + 1] = beta;
+            s.tau[k + 1] = taun;
+        }
+        for (int i = tid; i < mn; i += nt) s.V[(long long)(k + 2 + i) * n + k + 1] = vn[i];
+        // one pass: A <- A - v w^+ - w v^+ on rows/columns k+1.., and p_{k+1} = A' vn on
+        // rows/columns k+2..
+        for (int i = c0; i < m; i += 256) {
             const double2 vi = v[i], wi = w[i];
-            for (int j = tid & 31; j < m; j += 32) row[j] = c_rank2c(row[j], vi, w[j], wi, v[j]);
+            double2 acc = c_make(0.0, 0.0);
+            for (int j = q4; j < m; j += 4) {
+                double2& aji = A[(long long)(k + 1 + j) * n + k + 1 + i];
+                const double2 na = c_rank2c(aji, v[j], wi, w[j], vi);
+                aji = na;
+                if (j > 0 && i > 0) acc = c_fmac(na, vn[j - 1], acc);
+            }
+            if (i > 0) pp[q4][i - 1] = acc;
         }
         __syncthreads();
+        for (int i = tid; i < mn; i += nt) p[i] = c_add(c_add(pp[0][i], pp[1][i]), c_add(pp[2][i], pp[3][i]));
+        __syncthreads();
     }
-    if (tid == 0) {
-        s.d[n - 1] = A[(long long)(n - 1) * n + n - 1].x;
-        s.e[n - 1] = 0.0;
-        s.tau[n - 1] = c_make(0.0, 0.0);
+    if (n == 1 && tid == 0) {
+        s.d[0] = A[0].x;
+        s.e[0] = 0.0;
     }
 }
 
