@@ -724,11 +724,14 @@ hipError_t launch_big_forward(const BigLaunch& L, hipStream_t s) {
         const int k0 = blk * kBigB;
         const int bs = (n - 1 - k0) < kBigB ? (n - 1 - k0) : kBigB;
         BigGemm g{};
+        // the block's reflectors are zero above row k0 + 1: both products skip those rows
+        const long long r1 = (long long)(k0 + 1) * n;
+        const int mr = n - k0 - 1;
         // W = V_b^+ Z  (bs x n)
-        g.A = V + k0; g.lda = n; g.sa = pk;
-        g.B = U; g.ldb = n; g.sb = pk;
+        g.A = V + r1 + k0; g.lda = n; g.sa = pk;
+        g.B = U + r1; g.ldb = n; g.sb = pk;
         g.C = W; g.ldc = n; g.sc = pk;
-        g.M = bs; g.N = n; g.K = n; g.alpha = 1.0; g.beta = 0;
+        g.M = bs; g.N = n; g.K = mr; g.alpha = 1.0; g.beta = 0;
         if ((e = gemm(1, 0, g, L.count, s)) != hipSuccess) return e;
         // W2 = T W  (bs x n)
         g.A = TF + (long long)blk * kBigB * kBigB; g.lda = kBigB; g.sa = pk;
@@ -736,11 +739,11 @@ hipError_t launch_big_forward(const BigLaunch& L, hipStream_t s) {
         g.C = W2; g.ldc = n; g.sc = pk;
         g.M = bs; g.N = n; g.K = bs; g.alpha = 1.0; g.beta = 0;
         if ((e = gemm(0, 0, g, L.count, s)) != hipSuccess) return e;
-        // Z -= V_b W2  (n x n)
-        g.A = V + k0; g.lda = n; g.sa = pk;
+        // Z -= V_b W2  (rows k0 + 1 .. of Z)
+        g.A = V + r1 + k0; g.lda = n; g.sa = pk;
         g.B = W2; g.ldb = n; g.sb = pk;
-        g.C = U; g.ldc = n; g.sc = pk;
-        g.M = n; g.N = n; g.K = bs; g.alpha = -1.0; g.beta = 1;
+        g.C = U + r1; g.ldc = n; g.sc = pk;
+        g.M = mr; g.N = n; g.K = bs; g.alpha = -1.0; g.beta = 1;
         if ((e = gemm(0, 0, g, L.count, s)) != hipSuccess) return e;
     }
     // rotations: X = v U, then v' = U^+ X into the velocity's own buffer
