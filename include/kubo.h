@@ -121,8 +121,9 @@ typedef struct {
  * spreads each k-point over many workgroups: Householder reduction, bisection on
  * the split tridiagonal matrix, tridiagonal eigenvectors, a compact-WY
  * back-transformation and the rotations on batched matrix-core products; their
- * per-k-point slices (about 12 n^2 complex elements each, for up to 256 k-points
- * at a time) are part of the workspace.
+ * per-k-point slices (about 12 n^2 complex elements each, for up to KUBO_BIG_BATCH
+ * k-points at a time: environment variable read here, default 256, 1..4096) are
+ * part of the workspace.
  */
 kubo_status kubo_plan(kubo_plan_t* plan, const kubo_model_desc* models, int32_t n_models,
                       int32_t n_fermi, uint32_t flags, const kubo_tile* tiles, int32_t n_tiles,

@@ -77,6 +77,13 @@ struct CachedGraph {
     hipGraphExec_t exec = nullptr;
 };
 
+// k-points per pass of the large-n pipeline (KUBO_BIG_BATCH, default kBigBatch)
+int big_batch() {
+    const char* e = std::getenv("KUBO_BIG_BATCH");
+    long b = e ? std::atol(e) : kBigBatch;
+    return (int)std::min<long>(std::max<long>(b, 1), 4096);
+}
+
 size_t chunk_cap_bytes() {
     const char* e = std::getenv("KUBO_CHUNK_MB");
     long mb = e ? std::atol(e) : 2048;
@@ -113,6 +120,7 @@ struct kubo_plan_s {
            total = 0;
     size_t off_scratch = 0;
     size_t off_big = 0, big_bytes = 0;  // the large-n pipeline's slices
+    int big_batch = kBigBatch;          // k-points per pass of it
     long long slot_elems = 0;
     int wg_groups = 512;
     int n_queues = 0;  // per-k kernel launches (forward chunks, then backward), 8 counters each
@@ -475,12 +483,13 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
     // the large-n pipeline's per-k slices: room for a batch of up to kBigBatch
     // k-points of the largest such model, within four times the chunk cap
     P->big_bytes = 0;
+    P->big_batch = big_batch();
     for (const auto& md : P->models) {
         if (md.n <= 128) continue;
         long long most_k = 0;
         for (const Chunk& c : P->fwd.chunks) most_k = std::max(most_k, (long long)c.cls[kNumClasses - 1].count);
         const size_t slice = (size_t)big_layout(md.n).per_k * 16;
-        const size_t want = slice * (size_t)std::min<long long>(most_k, kBigBatch);
+        const size_t want = slice * (size_t)std::min<long long>(most_k, big_batch());
         P->big_bytes = std::max(P->big_bytes, std::max(slice, std::min(want, 4 * cap)));
     }
     P->off_big = off;
@@ -638,7 +647,7 @@ kubo_status enqueue_forward(kubo_plan_s* P, const double* t, const double* ef, d
                     const int n = P->models[m].n;
                     const long long per_k = big_layout(n).per_k;
                     const int batch = (int)std::max<long long>(
-                        1, std::min<long long>(kBigBatch, (long long)(P->big_bytes / 16) / per_k));
+                        1, std::min<long long>(P->big_batch, (long long)(P->big_bytes / 16) / per_k));
                     int j = i + 1;
                     while (j < c.cls[k].begin + c.cls[k].count && j - i < batch && items[j].model == m) ++j;
                     BigLaunch L{};
