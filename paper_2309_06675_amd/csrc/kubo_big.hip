@@ -7,7 +7,8 @@
 // in a slice of the workspace (row-major, complex):
 //   k_big_build    H, v_x, v_y from the pencil partial sums (many workgroups per k)
 //   k_big_tridiag  Householder reduction to real tridiagonal T (one 1024-thread
-//                  workgroup per k; the trailing matrix in the slice, L2-resident)
+//                  workgroup per k; the lower triangle of the trailing matrix in the
+//                  slice, one pass over it per step)
 //   k_big_eig      T split into unreduced blocks where an off-diagonal is negligible,
 //                  then every eigenvalue by Sturm bisection within its block (a thread each)
 //   k_big_vec      eigenvectors of T: a twisted factorisation per isolated eigenvalue,
@@ -113,16 +114,22 @@ __global__ __launch_bounds__(256) void k_big_build(BigLaunch a) {
 }
 
 // ---------------------------------------------------------------------------
-// step 2a: Householder reduction of H (Hermitian, full storage) to real
+// step 2a: Householder reduction of H (Hermitian, full storage on entry) to real
 // tridiagonal T = Q^+ H Q, Q = H_0 ... H_{n-2}, H_k = I - tau_k v_k v_k^+ with
 // v_k[k+1] = 1.  The reflectors go to V (column k, zero elsewhere), tau to tau,
 // the diagonal to d and the off-diagonal to e.  One workgroup per k-point.
-// The trailing matrix is bandwidth-bound, so step k's rank-2 update and step
-// k+1's product p = A v share one pass over it: column k+1 of the updated
-// matrix is formed first (from the old values and step k's v, w), giving
-// v_{k+1}; then every element is updated, written back and, for the rows and
-// columns of step k+1, accumulated into p_{k+1} (p_i = sum_j conj(A_ji) v_j, four
-// threads per column i reading rows j).
+// The reduction is bound by the traffic of the trailing matrix, so (i) step k's
+// rank-2 update and step k+1's product p = A v share one pass over it: column
+// k+1 of the updated matrix is formed first (from the old values and step k's
+// v, w), giving v_{k+1}; then the rest is updated, written back and accumulated
+// into p_{k+1}; and (ii) after step 0 only the lower triangle (diagonal
+// included) is read and written, each element serving both halves of the
+// Hermitian product: A_ji (j > i) adds A_ji v_i to p_j (the row part) and
+// conj(A_ji) v_j to p_i (the column part).  Wavefront w owns the rows j = w mod
+// 16 of the triangle, lanes over 64-column segments of a row: its row parts are
+// summed across the lanes (complete, as the row is its own), its column parts
+// stay in registers per segment and are combined across the 16 wavefronts in a
+// fixed order, so the result does not depend on scheduling.
 // ---------------------------------------------------------------------------
 namespace {
 
@@ -163,8 +170,28 @@ __device__ __forceinline__ double2 big_reflector(double2* v, int m, double xn2, 
 
 }  // namespace
 
+// Sums q[0..3] (two complex numbers) over the 64 lanes by recursive halving:
+// lanes 0, 16, 32, 48 end with the sums of q[0], q[1], q[2], q[3].
+__device__ __forceinline__ double big_lane_sum4(double q0, double q1, double q2, double q3) {
+    const int l = threadIdx.x & 63;
+    const bool hi32 = (l & 32) != 0, hi16 = (l & 16) != 0;
+    // offset 32: the lower half keeps q0, q1, the upper half q2, q3
+    const double s0 = hi32 ? q0 : q2, s1 = hi32 ? q1 : q3;
+    double k0 = hi32 ? q2 : q0, k1 = hi32 ? q3 : q1;
+    k0 += __shfl_xor(s0, 32, 64);
+    k1 += __shfl_xor(s1, 32, 64);
+    // offset 16: keep one of the two
+    double r = hi16 ? k1 : k0;
+    r += __shfl_xor(hi16 ? k0 : k1, 16, 64);
+    for (int off = 8; off >= 1; off >>= 1) r += __shfl_xor(r, off, 64);
+    return r;
+}
+
+// NS: 64-column segments a row of the trailing triangle can span; RB: rows a
+// wavefront takes at a time (their loads in flight together)
+template <int NS, int RB>
 __global__ __launch_bounds__(1024) void k_big_tridiag(BigLaunch a) {
-    __shared__ double2 vb[2][kBigMaxN], w[kBigMaxN], p[kBigMaxN], pp[4][kBigMaxN];
+    __shared__ double2 vb[2][kBigMaxN], w[kBigMaxN], p[kBigMaxN], cb[8][kBigMaxN];
     __shared__ double red[16];
     __shared__ double2 sh[2];
     __shared__ double shb;
@@ -173,8 +200,10 @@ __global__ __launch_bounds__(1024) void k_big_tridiag(BigLaunch a) {
     const BigSlice s = big_slice(a, b);
     double2* A = s.H;
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int q4 = tid >> 8, c0 = tid & 255;  // four threads per column
+    const int q4 = tid >> 8, c0 = tid & 255;  // step 0: four threads per column
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     double2 tau_cur;  // tau of the current step, in every thread
+    double2(*pp)[kBigMaxN] = cb;
     // step 0: reflector of column 0 and p_0 = A v_0 (a plain pass)
     {
         const int m = n - 1;
@@ -244,21 +273,82 @@ __global__ __launch_bounds__(1024) void k_big_tridiag(BigLaunch a) {
             s.tau[k + 1] = taun;
         }
         for (int i = tid; i < mn; i += nt) s.V[(long long)(k + 2 + i) * n + k + 1] = vn[i];
-        // one pass: A <- A - v w^+ - w v^+ on rows/columns k+1.., and p_{k+1} = A' vn on
-        // rows/columns k+2..
-        for (int i = c0; i < m; i += 256) {
-            const double2 vi = v[i], wi = w[i];
-            double2 acc = c_make(0.0, 0.0);
-            for (int j = q4; j < m; j += 4) {
-                double2& aji = A[(long long)(k + 1 + j) * n + k + 1 + i];
-                const double2 na = c_rank2c(aji, v[j], wi, w[j], vi);
-                aji = na;
-                if (j > 0 && i > 0) acc = c_fmac(na, vn[j - 1], acc);
+        // one pass over the lower triangle of rows/columns k+2.. (local x = global -
+        // k - 2): A <- A - v w^+ - w v^+, and p_{k+1} = A' vn.  Column k+1 is done
+        // (it gave vn), so it is neither updated nor stored.
+        double2* const A0 = A + (long long)(k + 2) * n + (k + 2);
+        const double2* const v1 = v + 1;
+        const double2* const w1 = w + 1;
+        double2 pc[NS];
+#pragma unroll
+        for (int sg = 0; sg < NS; ++sg) pc[sg] = c_make(0.0, 0.0);
+        for (int j0 = wv; j0 < mn; j0 += 16 * RB) {
+            double2 av[RB][NS];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const int jx = j0 + 16 * r;
+#pragma unroll
+                for (int sg = 0; sg < NS; ++sg) {
+                    const int ix = 64 * sg + lane;
+                    av[r][sg] = c_make(0.0, 0.0);
+                    if (jx < mn && ix <= jx) av[r][sg] = A0[(long long)jx * n + ix];
+                }
             }
-            if (i > 0) pp[q4][i - 1] = acc;
+            double rs[RB][2];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const int jx = j0 + 16 * r;
+                double2 acc = c_make(0.0, 0.0);
+                if (jx < mn) {
+                    const double2 vj = v1[jx], wj = w1[jx], vnj = vn[jx];
+#pragma unroll
+                    for (int sg = 0; sg < NS; ++sg) {
+                        const int ix = 64 * sg + lane;
+                        if (ix <= jx) {
+                            const double2 na = c_rank2c(av[r][sg], vj, w1[ix], wj, v1[ix]);
+                            A0[(long long)jx * n + ix] = na;
+                            pc[sg] = c_fmac(na, vnj, pc[sg]);
+                            if (ix < jx) acc = c_fma(na, vn[ix], acc);
+                        }
+                    }
+                }
+                rs[r][0] = acc.x;
+                rs[r][1] = acc.y;
+            }
+            // the row parts: lanes 0/16 (and 32/48) end with row j0's (j0 + 16's) sum
+#pragma unroll
+            for (int r = 0; r < RB; r += 2) {
+                const double q2 = (r + 1 < RB) ? rs[r + 1][0] : 0.0;
+                const double q3 = (r + 1 < RB) ? rs[r + 1][1] : 0.0;
+                const double sum = big_lane_sum4(rs[r][0], rs[r][1], q2, q3);
+                const int jx = j0 + 16 * (r + (lane >> 5));
+                if ((lane & 15) == 0 && jx < mn && (r + (lane >> 5)) < RB)
+                    reinterpret_cast<double*>(p)[2 * jx + ((lane >> 4) & 1)] = sum;
+            }
+        }
+        // the column parts: wavefronts 8..15 hand theirs to 0..7, which add their own
+        if (wv >= 8) {
+#pragma unroll
+            for (int sg = 0; sg < NS; ++sg) {
+                const int ix = 64 * sg + lane;
+                if (ix < mn) cb[wv - 8][ix] = pc[sg];
+            }
         }
         __syncthreads();
-        for (int i = tid; i < mn; i += nt) p[i] = c_add(c_add(pp[0][i], pp[1][i]), c_add(pp[2][i], pp[3][i]));
+        if (wv < 8) {
+#pragma unroll
+            for (int sg = 0; sg < NS; ++sg) {
+                const int ix = 64 * sg + lane;
+                if (ix < mn) cb[wv][ix] = c_add(cb[wv][ix], pc[sg]);
+            }
+        }
+        __syncthreads();
+        for (int i = tid; i < mn; i += nt) {
+            double2 t = p[i];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) t = c_add(t, cb[u][i]);
+            p[i] = t;
+        }
         __syncthreads();
     }
     if (n == 1 && tid == 0) {
@@ -700,7 +790,10 @@ hipError_t launch_big_forward(const BigLaunch& L, hipStream_t s) {
     hipLaunchKernelGGL(k_big_build, dim3((unsigned)((nn + 255) / 256 < 64 ? (nn + 255) / 256 : 64), L.count),
                        dim3(256), 0, s, L);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_big_tridiag, dim3(L.count), dim3(1024), 0, s, L);
+    if (L.n <= 258)
+        hipLaunchKernelGGL((k_big_tridiag<4, 2>), dim3(L.count), dim3(1024), 0, s, L);
+    else
+        hipLaunchKernelGGL((k_big_tridiag<8, 1>), dim3(L.count), dim3(1024), 0, s, L);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_big_eig, dim3(L.count), dim3(kBigMaxN), 0, s, L);
     if ((e = hipGetLastError()) != hipSuccess) return e;

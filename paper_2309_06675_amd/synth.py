@@ -193,7 +193,7 @@ def random_unitary(n: int, seed: int) -> np.ndarray:
 
 def rotate_orbitals(a: TBModel, W: np.ndarray) -> TBModel:
     """t(R) -> W t(R) W^+ (a change of orbital basis)."""
-    return TBModel(t=np.einsum("ij,rjk,lk->ril", W, a.t, W.conj()), R=a.R.copy())
+    return TBModel(t=np.ascontiguousarray(W @ a.t @ W.conj().T), R=a.R.copy())
 
 
 def qwz_plane_model(u: float, plane: str) -> TBModel:

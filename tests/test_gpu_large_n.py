@@ -73,3 +73,30 @@ def test_large_n_mixed_plan_and_slab(torch, oracle):
                           with_sabs=True)
     assert_sigma_parity(got[0], ref0, s0, what="large mixed small n=20")
     assert_sigma_parity(got[1], ref1, s1, what="large mixed n=150 slab")
+
+
+@pytest.mark.parametrize("parts,grid", [((150, 150), (1, 2, 2)), ((128, 128, 128, 128), (1, 1, 2))])
+def test_large_n_rotated_direct_sum(torch, oracle, parts, grid):
+    """n above 256, up to the 512 maximum: W (A (+) B (+) ...) W^+ with a random unitary W
+    is a dense model whose sigma is exactly the sum of its blocks' (a k-independent change
+    of orbital basis leaves every band's curvature unchanged, and bands of different
+    blocks have no velocity matrix elements between them), so the oracle runs on the
+    blocks alone."""
+    blocks = [synth.random_model(p, 1, 1.0, 9400 + 10 * i + p) for i, p in enumerate(parts)]
+    m = blocks[0]
+    for b in blocks[1:]:
+        m = synth.direct_sum(m, b)
+    m = synth.rotate_orbitals(m, synth.random_unitary(m.n, 9499 + m.n))
+    assert m.n == sum(parts)
+    ranges = [oracle.band_range(b.t, b.R, (1, 1, 1)) for b in blocks]
+    lo, hi = min(r[0] for r in ranges), max(r[1] for r in ranges)
+    ef = np.linspace(lo + 0.1 * (hi - lo), hi - 0.1 * (hi - lo), 5)
+    print(f"case large rotated direct sum n={m.n} grid={grid}", flush=True)
+    got = run(torch, [m], grid, ef, 1e-3, 0.01)
+    ref = np.zeros(ef.size)
+    sabs = np.zeros(ef.size)
+    for b in blocks:
+        r, s = oracle.ahc(b.t, b.R, grid, ef, 1e-3, 0.01, with_sabs=True)
+        ref += r
+        sabs += s
+    assert_sigma_parity(got[0], ref, sabs, what=f"large rotated direct sum n={m.n}")
