@@ -697,9 +697,13 @@ __device__ void wave_stage_velocity(WaveLds<NP>& S, int n, int nR0, const double
         double2 cf = S.ph[rho];
         if (is_x) cf = c_scale((double)r0[rho], c_i(cf));
         const double2* Tr = T + (long long)rho * nn;
+        // unconditional loads (padding from element 0, then zeroed): all in flight together
+        double2 tv[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) tv[q] = Tr[off[q] >= 0 ? off[q] : 0];
 #pragma unroll
         for (int q = 0; q < PER; ++q)
-            if (off[q] >= 0) acc[q] = c_fma(cf, Tr[off[q]], acc[q]);
+            acc[q] = c_fma(cf, (off[q] >= 0) ? tv[q] : c_make(0.0, 0.0), acc[q]);
     }
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
@@ -950,13 +954,16 @@ __device__ bool wave_eigen(WaveLds<NP>& S, const ModelDev& md, const double2* __
             const double2 ph = S.ph[rho];
             const double2 cf = c_scale((double)r0[rho], c_i(ph));
             const double2* Tr = T0 + (long long)rho * nn;
+            // every lane loads (padding from element 0, then zeroed), so that the
+            // loads are not each behind a branch and a wait of their own
+            double2 tv[PER];
+#pragma unroll
+            for (int q = 0; q < PER; ++q) tv[q] = Tr[off[q] >= 0 ? off[q] : 0];
 #pragma unroll
             for (int q = 0; q < PER; ++q) {
-                if (off[q] >= 0) {
-                    const double2 tv = Tr[off[q]];
-                    acc[q] = c_fma(tv, ph, acc[q]);
-                    accx[q] = c_fma(cf, tv, accx[q]);
-                }
+                const double2 t = (off[q] >= 0) ? tv[q] : c_make(0.0, 0.0);
+                acc[q] = c_fma(t, ph, acc[q]);
+                accx[q] = c_fma(cf, t, accx[q]);
             }
         }
 #pragma unroll

@@ -192,11 +192,26 @@ __device__ void wg_build(WgLds& S, const WgScratch& X, const ModelDev& md,
         const int j = i + (e - (i * n - (i * (i - 1)) / 2));
         const long long off = (long long)i * n + j;
         double2 h = c_make(0.0, 0.0), x = h, y = h;
-        for (int rho = 0; rho < md.nR0; ++rho) {
-            const double2 p0 = c_mul(T0[(long long)rho * nn + off], S.ph[rho]);
-            h = c_add(h, p0);
-            x = c_add(x, c_scale((double)r0[rho], c_i(p0)));
-            y = c_fma(T1[(long long)rho * nn + off], S.ph[rho], y);
+        // four rho terms' loads issued together (the index clamped, so every load is
+        // valid), then their sums
+        for (int r4 = 0; r4 < md.nR0; r4 += 4) {
+            double2 t0[4], t1[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const long long o = (long long)min(r4 + u, md.nR0 - 1) * nn + off;
+                t0[u] = T0[o];
+                t1[u] = T1[o];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int rho = r4 + u;
+                if (rho < md.nR0) {
+                    const double2 p0 = c_mul(t0[u], S.ph[rho]);
+                    h = c_add(h, p0);
+                    x = c_add(x, c_scale((double)r0[rho], c_i(p0)));
+                    y = c_fma(t1[u], S.ph[rho], y);
+                }
+            }
         }
         if (i == j) {
             h.y = 0.0;
