@@ -135,7 +135,8 @@ template <int NP>
 __device__ void wave_tridiag(WaveLds<NP>& S, int n, double& d_lane, double& e_lane) {
     constexpr int LD = WaveLds<NP>::LD;
     constexpr int HW = NP / 2;
-    const int lane = threadIdx.x & 63;
+    int lane = threadIdx.x & 63;
+    asm volatile("" : "+v"(lane));  // recomputed here, not hoisted out of the k loop
     const int i = lane >> 1, h = lane & 1;
     const bool row_ok = i < n;
     // reciprocal: hardware estimate and one Newton step
