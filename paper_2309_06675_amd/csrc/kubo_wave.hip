@@ -207,16 +207,15 @@ __device__ void wave_tridiag(WaveLds<NP>& S, int n, double& d_lane, double& e_la
         if (h == 0 && i < NP) S.vv[i] = v;
         __syncthreads();
         if (tau.x == 0.0 && tau.y == 0.0) continue;
-        // p = A v (row i), the two halves combined within the lane pair
+        // p = A v (row i), the two halves combined within the lane pair; v is read
+        // whole (broadcast reads, one wait) and only the live groups are multiplied
         double2 vc[HW];
+#pragma unroll
+        for (int jj = 0; jj < HW; ++jj) vc[jj] = S.vv[2 * jj + h];
         double2 p = c_make(0.0, 0.0);
 #pragma unroll
         for (int gq = 0; gq < HW / 4; ++gq) {
-#pragma unroll
-            for (int t = 0; t < 4; ++t) vc[4 * gq + t] = c_make(0.0, 0.0);
             if (8 * gq + 7 > k) {  // some column of this group of four slots is still live
-#pragma unroll
-                for (int t = 0; t < 4; ++t) vc[4 * gq + t] = S.vv[2 * (4 * gq + t) + h];
 #pragma unroll
                 for (int t = 0; t < 4; ++t) p = c_fma(a[4 * gq + t], vc[4 * gq + t], p);
             }
@@ -229,16 +228,16 @@ __device__ void wave_tridiag(WaveLds<NP>& S, int n, double& d_lane, double& e_la
         if (h == 0 && i < NP) S.wv[i] = w;
         __syncthreads();
         // A <- A - v w^+ - w v^+ (v_c = w_c = 0 for c <= k keeps the stored reflectors)
+        double2 wc[HW];
+#pragma unroll
+        for (int jj = 0; jj < HW; ++jj) wc[jj] = S.wv[2 * jj + h];
 #pragma unroll
         for (int gq = 0; gq < HW / 4; ++gq) {
             if (8 * gq + 7 > k) {
-                double2 wc[4];
-#pragma unroll
-                for (int t = 0; t < 4; ++t) wc[t] = S.wv[2 * (4 * gq + t) + h];
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     const int jj = 4 * gq + t;
-                    a[jj] = c_rank2c(a[jj], v, wc[t], w, vc[jj]);
+                    a[jj] = c_rank2c(a[jj], v, wc[jj], w, vc[jj]);
                 }
             }
         }
