@@ -1065,16 +1065,30 @@ __device__ void wg_gemm_lds(WgLds& S, double2* __restrict__ C, int n, int nk, FA
                 ci[a][b] = zero;
             }
         for (int kb = 0; kb < nk; kb += kWgKT) {
-            __syncthreads();
-            for (int e = tid; e < 64 * kWgKT; e += kWgThreads) {
+            // the tiles' elements of this thread: every load issued first (indices
+            // clamped into the matrices, so each is valid), zeros outside stored after
+            constexpr int PER = 64 * kWgKT / kWgThreads;
+            double2 ta[PER], tb[PER];
+#pragma unroll
+            for (int r = 0; r < PER; ++r) {
+                const int e = tid + r * kWgThreads;
                 const int ii = A_IFAST ? (e & 63) : (e / kWgKT);
                 const int kk = A_IFAST ? (e >> 6) : (e - (e / kWgKT) * kWgKT);
-                const int gi = i0 + ii, gk = kb + kk;
-                As[ii * kWgLdA + kk] = (gi < n && gk < nk) ? LA(gi, gk) : c_make(0.0, 0.0);
+                ta[r] = LA(min(i0 + ii, n - 1), min(kb + kk, nk - 1));
                 const int jj = B_KFAST ? (e / kWgKT) : (e & 63);
                 const int k2 = B_KFAST ? (e - (e / kWgKT) * kWgKT) : (e >> 6);
-                const int gj = j0 + jj, gk2 = kb + k2;
-                Bs[k2 * kWgLdB + jj] = (gk2 < nk && gj < n) ? LB(gk2, gj) : c_make(0.0, 0.0);
+                tb[r] = LB(min(kb + k2, nk - 1), min(j0 + jj, n - 1));
+            }
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < PER; ++r) {
+                const int e = tid + r * kWgThreads;
+                const int ii = A_IFAST ? (e & 63) : (e / kWgKT);
+                const int kk = A_IFAST ? (e >> 6) : (e - (e / kWgKT) * kWgKT);
+                As[ii * kWgLdA + kk] = (i0 + ii < n && kb + kk < nk) ? ta[r] : c_make(0.0, 0.0);
+                const int jj = B_KFAST ? (e / kWgKT) : (e & 63);
+                const int k2 = B_KFAST ? (e - (e / kWgKT) * kWgKT) : (e >> 6);
+                Bs[k2 * kWgLdB + jj] = (kb + k2 < nk && j0 + jj < n) ? tb[r] : c_make(0.0, 0.0);
             }
             __syncthreads();
 #pragma unroll
