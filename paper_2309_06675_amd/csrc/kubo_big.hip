@@ -673,27 +673,44 @@ __global__ __launch_bounds__(256) void k_big_gemm(BigGemm g) {
             cr[x][y] = zero;
             ci[x][y] = zero;
         }
-    for (int kb = 0; kb < g.K; kb += KT) {
-        __syncthreads();
-        for (int e = tid; e < 64 * KT; e += 256) {
-            // A panel: op(A)(i, k), rows i0.., inner kb..
+    // panel elements of this thread: loaded into registers one panel ahead (indices
+    // clamped into the matrices, so every load is valid and none waits behind a
+    // branch), stored to LDS with zeros outside the matrices
+    constexpr int PER = 64 * KT / 256;
+    double2 ra[PER], rb[PER];
+    auto load_panel = [&](int kb) {
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            const int e = tid + 256 * r;
             {
                 const int ii = OPA ? (e & 63) : (e / KT), kk = OPA ? (e >> 6) : (e - (e / KT) * KT);
-                const int gi = i0 + ii, gk = kb + kk;
-                double2 v = c_make(0.0, 0.0);
-                if (gi < g.M && gk < g.K) v = OPA ? c_conj(A[(long long)gk * g.lda + gi]) : A[(long long)gi * g.lda + gk];
-                As[ii * LDA + kk] = v;
+                const int gi = min(i0 + ii, g.M - 1), gk = min(kb + kk, g.K - 1);
+                ra[r] = OPA ? c_conj(A[gk * g.lda + gi]) : A[gi * g.lda + gk];
             }
-            // B panel: op(B)(k, j)
             {
                 const int jj = OPB ? (e / KT) : (e & 63), kk = OPB ? (e - (e / KT) * KT) : (e >> 6);
-                const int gj = j0 + jj, gk = kb + kk;
-                double2 v = c_make(0.0, 0.0);
-                if (gj < g.N && gk < g.K) v = OPB ? c_conj(B[(long long)gj * g.ldb + gk]) : B[(long long)gk * g.ldb + gj];
-                Bs[kk * LDB + jj] = v;
+                const int gj = min(j0 + jj, g.N - 1), gk = min(kb + kk, g.K - 1);
+                rb[r] = OPB ? c_conj(B[gj * g.ldb + gk]) : B[gk * g.ldb + gj];
+            }
+        }
+    };
+    load_panel(0);
+    for (int kb = 0; kb < g.K; kb += KT) {
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            const int e = tid + 256 * r;
+            {
+                const int ii = OPA ? (e & 63) : (e / KT), kk = OPA ? (e >> 6) : (e - (e / KT) * KT);
+                As[ii * LDA + kk] = (i0 + ii < g.M && kb + kk < g.K) ? ra[r] : c_make(0.0, 0.0);
+            }
+            {
+                const int jj = OPB ? (e / KT) : (e & 63), kk = OPB ? (e - (e / KT) * KT) : (e >> 6);
+                Bs[kk * LDB + jj] = (j0 + jj < g.N && kb + kk < g.K) ? rb[r] : c_make(0.0, 0.0);
             }
         }
         __syncthreads();
+        if (kb + KT < g.K) load_panel(kb + KT);  // in flight during this panel's products
 #pragma unroll
         for (int k4 = 0; k4 < KT / 4; ++k4) {
             double2 av[2], bv[2];
