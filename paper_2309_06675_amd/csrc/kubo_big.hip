@@ -359,28 +359,34 @@ __global__ __launch_bounds__(1024) void k_big_tridiag(BigLaunch a) {
 
 // ---------------------------------------------------------------------------
 // step 2b: eigenvalues.  T splits where |e_i| <= eps (|d_i| + |d_i+1|); within an
-// unreduced block every eigenvalue is simple, found by Sturm bisection on the
-// block (ratio form with a pivot floor) to 4 eps max|lambda|.  Thread j takes the
-// j-th eigenvalue in block order (eigenvalues are not sorted: nothing downstream
-// needs an order).
+// unreduced block every eigenvalue is simple, found from Sturm counts on the block
+// (ratio form with a pivot floor, d and e staged in LDS) to 4 eps max|lambda|: by
+// trisection with two lanes per eigenvalue when 2n threads fit the block, else by
+// bisection.  The j-th eigenvalue in block order goes to thread (pair) j
+// (eigenvalues are not sorted: nothing downstream needs an order).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBigMaxN) void k_big_eig(BigLaunch a) {
     __shared__ int bstart[kBigMaxN], bsize[kBigMaxN], boff[kBigMaxN];
+    __shared__ double dd[kBigMaxN], ee[kBigMaxN];
     __shared__ int nblk;
     __shared__ double sh_lo, sh_hi, sh_emax;
     const int b = blockIdx.x;
     const int n = a.n;
     const BigSlice s = big_slice(a, b);
-    const int j = threadIdx.x;
-    if (j == 0) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        dd[i] = s.d[i];
+        ee[i] = s.e[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
         double lo = 1e300, hi = -1e300, emax = 0.0;
         int nb = 0, start = 0;
         for (int i = 0; i < n; ++i) {
-            const double ep = (i > 0) ? fabs(s.e[i - 1]) : 0.0, en = (i < n - 1) ? fabs(s.e[i]) : 0.0;
-            lo = fmin(lo, s.d[i] - ep - en);
-            hi = fmax(hi, s.d[i] + ep + en);
+            const double ep = (i > 0) ? fabs(ee[i - 1]) : 0.0, en = (i < n - 1) ? fabs(ee[i]) : 0.0;
+            lo = fmin(lo, dd[i] - ep - en);
+            hi = fmax(hi, dd[i] + ep + en);
             emax = fmax(emax, en);
-            const bool cut = (i == n - 1) || en <= 2.220446049250313e-16 * (fabs(s.d[i]) + fabs(s.d[i + 1]));
+            const bool cut = (i == n - 1) || en <= 2.220446049250313e-16 * (fabs(dd[i]) + fabs(dd[i + 1]));
             if (cut) {
                 bstart[nb] = start;
                 bsize[nb] = i + 1 - start;
@@ -395,13 +401,34 @@ __global__ __launch_bounds__(kBigMaxN) void k_big_eig(BigLaunch a) {
         sh_emax = emax;
     }
     __syncthreads();
-    if (j >= n) return;
+    // two lanes of a wavefront per eigenvalue when the block has the threads for it:
+    // each pass they count at the two points that cut the interval in thirds and
+    // keep the third holding the eigenvalue; otherwise one thread bisects
+    const bool pair = 2 * n <= (int)blockDim.x;
+    const int j = pair ? (threadIdx.x >> 1) : threadIdx.x;
+    const int half = pair ? (threadIdx.x & 1) : 0;
+    if (j >= n) return;  // whole pairs leave together
     int bi = 0;
     while (bi + 1 < nblk && boff[bi + 1] <= j) ++bi;
     const int st = bstart[bi], m = bsize[bi], jl = j - st;
     const double scale = fmax(fabs(sh_lo), fabs(sh_hi));
     const double tol = 4.0 * 2.220446049250313e-16 * scale + 1e-300;
     const double pivmin = 1e-290 * fmax(1.0, sh_emax * sh_emax);
+    // eigenvalues of the block below x (Sturm count of the ratio recurrence)
+    auto count = [&](double x) {
+        int cnt = 0;
+        double q = 1.0;
+        for (int i = st; i < st + m; ++i) {
+            const double e2 = (i > st) ? ee[i - 1] * ee[i - 1] : 0.0;
+            double r = __builtin_amdgcn_rcp(q);
+            r = fma(r, fma(-q, r, 1.0), r);
+            double qi = fma(-e2, r, dd[i] - x);
+            if (fabs(qi) < pivmin) qi = -pivmin;
+            cnt += (qi < 0.0) ? 1 : 0;
+            q = qi;
+        }
+        return cnt;
+    };
     double lo = sh_lo, hi = sh_hi;
     bool ok = false;
     for (int pass = 0; pass < 200; ++pass) {
@@ -409,24 +436,31 @@ __global__ __launch_bounds__(kBigMaxN) void k_big_eig(BigLaunch a) {
             ok = true;
             break;
         }
-        const double x = 0.5 * (lo + hi);
-        int cnt = 0;
-        double q = 1.0;
-        for (int i = st; i < st + m; ++i) {
-            const double e2 = (i > st) ? s.e[i - 1] * s.e[i - 1] : 0.0;
-            double r = __builtin_amdgcn_rcp(q);
-            r = fma(r, fma(-q, r, 1.0), r);
-            double qi = fma(-e2, r, s.d[i] - x);
-            if (fabs(qi) < pivmin) qi = -pivmin;
-            cnt += (qi < 0.0) ? 1 : 0;
-            q = qi;
+        if (pair) {
+            const double t = (hi - lo) * (1.0 / 3.0);
+            const double x1 = lo + t, x2 = hi - t;  // the same in both lanes
+            const int c = count(half ? x2 : x1);
+            const int co = __shfl_xor(c, 1);
+            const int c1 = half ? co : c, c2 = half ? c : co;
+            if (c1 > jl) {
+                hi = x1;
+            } else if (c2 > jl) {
+                lo = x1;
+                hi = x2;
+            } else {
+                lo = x2;
+            }
+        } else {
+            const double x = 0.5 * (lo + hi);
+            if (count(x) <= jl) lo = x;
+            else hi = x;
         }
-        if (cnt <= jl) lo = x;
-        else hi = x;
     }
-    s.E[j] = 0.5 * (lo + hi);
-    s.blk[j] = st | (m << 16);
-    if (!ok) atomicOr(a.status, kStatNoConv);
+    if (half == 0) {
+        s.E[j] = 0.5 * (lo + hi);
+        s.blk[j] = st | (m << 16);
+        if (!ok) atomicOr(a.status, kStatNoConv);
+    }
 }
 
 // ---------------------------------------------------------------------------
