@@ -537,19 +537,24 @@ __device__ void big_tri_solve(const double* d, const double* e, int st, int m, d
 }
 
 __global__ __launch_bounds__(kBigMaxN) void k_big_vec(BigLaunch a) {
+    __shared__ double dd[kBigMaxN], ee[kBigMaxN];  // T, read by every thread's recurrences
     const int b = blockIdx.x;
     const int n = a.n;
     const BigSlice s = big_slice(a, b);
     const int j = threadIdx.x;
     for (long long e = j; e < (long long)n * n; e += blockDim.x) s.U[e] = c_make(0.0, 0.0);
+    for (int i = j; i < n; i += blockDim.x) {
+        dd[i] = s.d[i];
+        ee[i] = s.e[i];
+    }
     __syncthreads();
     if (j >= n) return;
     const int st = s.blk[j] & 0xffff, m = s.blk[j] >> 16;
     const double lam = s.E[j];
     double span = 0.0, emax = 0.0;
     for (int i = st; i < st + m; ++i) {
-        span = fmax(span, fabs(s.d[i]) + ((i > st) ? fabs(s.e[i - 1]) : 0.0) + ((i < st + m - 1) ? fabs(s.e[i]) : 0.0));
-        emax = fmax(emax, (i < st + m - 1) ? fabs(s.e[i]) : 0.0);
+        span = fmax(span, fabs(dd[i]) + ((i > st) ? fabs(ee[i - 1]) : 0.0) + ((i < st + m - 1) ? fabs(ee[i]) : 0.0));
+        emax = fmax(emax, (i < st + m - 1) ? fabs(ee[i]) : 0.0);
     }
     const double pivmin = 1e-290 * fmax(1.0, emax * emax);
     const double gapmin = kBigGap * fmax(span, 1e-300);
@@ -562,14 +567,14 @@ __global__ __launch_bounds__(kBigMaxN) void k_big_vec(BigLaunch a) {
         // twisted factorisation of T - lam I on the block
         double q = 1.0;
         for (int i = 0; i < m; ++i) {
-            double qi = (s.d[st + i] - lam) - ((i > 0) ? s.e[st + i - 1] * s.e[st + i - 1] / q : 0.0);
+            double qi = (dd[st + i] - lam) - ((i > 0) ? ee[st + i - 1] * ee[st + i - 1] / q : 0.0);
             if (fabs(qi) < pivmin) qi = -pivmin;
             dp[i] = qi;
             q = qi;
         }
         q = 1.0;
         for (int i = m - 1; i >= 0; --i) {
-            double qi = (s.d[st + i] - lam) - ((i < m - 1) ? s.e[st + i] * s.e[st + i] / q : 0.0);
+            double qi = (dd[st + i] - lam) - ((i < m - 1) ? ee[st + i] * ee[st + i] / q : 0.0);
             if (fabs(qi) < pivmin) qi = -pivmin;
             dm[i] = qi;
             q = qi;
@@ -577,7 +582,7 @@ __global__ __launch_bounds__(kBigMaxN) void k_big_vec(BigLaunch a) {
         int r = 0;
         double best = 1e300;
         for (int i = 0; i < m; ++i) {
-            const double g = dp[i] + dm[i] - (s.d[st + i] - lam);
+            const double g = dp[i] + dm[i] - (dd[st + i] - lam);
             if (fabs(g) < best) {
                 best = fabs(g);
                 r = i;
@@ -587,13 +592,13 @@ __global__ __launch_bounds__(kBigMaxN) void k_big_vec(BigLaunch a) {
         double nrm = 1.0;
         dp[r] = 1.0;  // dp reused for z
         for (int i = r - 1; i >= 0; --i) {
-            const double z = -s.e[st + i] * dp[i + 1] / dp[i];
+            const double z = -ee[st + i] * dp[i + 1] / dp[i];
             dp[i] = z;
             nrm += z * z;
         }
         double zp = 1.0;
         for (int i = r + 1; i < m; ++i) {
-            const double z = -s.e[st + i - 1] * zp / dm[i];
+            const double z = -ee[st + i - 1] * zp / dm[i];
             dm[i] = z;
             zp = z;
             nrm += z * z;
@@ -622,7 +627,7 @@ __global__ __launch_bounds__(kBigMaxN) void k_big_vec(BigLaunch a) {
         const double lc = s.E[c] + (double)(c - j) * 2.220446049250313e-16 * span;  // separate the shifts
         for (int i = 0; i < m; ++i) x[i] = big_start(c, i);
         for (int itr = 0; itr < 3; ++itr) {
-            big_tri_solve(s.d, s.e, st, m, lc, floor_solve, x, u0, u1, u2, l, pv);
+            big_tri_solve(dd, ee, st, m, lc, floor_solve, x, u0, u1, u2, l, pv);
             // orthogonalise against the cluster's earlier members (modified Gram-Schmidt)
             for (int c2 = j; c2 < c; ++c2) {
                 double dot = 0.0;
