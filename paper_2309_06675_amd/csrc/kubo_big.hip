@@ -660,9 +660,25 @@ __global__ __launch_bounds__(256) void k_big_tfac(BigLaunch a) {
     for (int e = threadIdx.x; e < kBigB * kBigB; e += blockDim.x) {
         const int i = e / kBigB, j = e - (e / kBigB) * kBigB;
         double2 acc = c_make(0.0, 0.0);
-        if (i < j && j < bs)
-            for (int r = k0 + j + 1; r < n; ++r)
-                acc = c_fmac(s.V[(long long)r * n + k0 + i], s.V[(long long)r * n + k0 + j], acc);
+        if (i < j && j < bs) {
+            // four rows at a time into four sums, so that eight loads are in flight
+            const double2* vi = s.V + k0 + i;
+            const double2* vj = s.V + k0 + j;
+            double2 a4[4] = {acc, acc, acc, acc};
+            int r = k0 + j + 1;
+            for (; r + 3 < n; r += 4) {
+                double2 x[4], y[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    x[u] = vi[(long long)(r + u) * n];
+                    y[u] = vj[(long long)(r + u) * n];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) a4[u] = c_fmac(x[u], y[u], a4[u]);
+            }
+            for (; r < n; ++r) a4[0] = c_fmac(vi[(long long)r * n], vj[(long long)r * n], a4[0]);
+            acc = c_add(c_add(a4[0], a4[1]), c_add(a4[2], a4[3]));
+        }
         C[i][j] = acc;
         T[i][j] = c_make(0.0, 0.0);
     }
