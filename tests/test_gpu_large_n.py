@@ -100,3 +100,15 @@ def test_large_n_rotated_direct_sum(torch, oracle, parts, grid):
         ref += r
         sabs += s
     assert_sigma_parity(got[0], ref, sabs, what=f"large rotated direct sum n={m.n}")
+
+
+def test_large_n_ragged_batches(torch, oracle, monkeypatch):
+    """KUBO_BIG_BATCH = 5 on 12 k-points: passes of 5, 5 and 2 k-points through the pipeline."""
+    monkeypatch.setenv("KUBO_BIG_BATCH", "5")
+    m = synth.random_model(136, 1, 1.0, 9500)
+    grid = (3, 2, 2)
+    ef = _levels(oracle, m, 4)
+    print("case large ragged batches n=136", flush=True)
+    got = run(torch, [m], grid, ef, 1e-3, 0.01)
+    ref, sabs = oracle.ahc(m.t, m.R, grid, ef, 1e-3, 0.01, with_sabs=True)
+    assert_sigma_parity(got[0], ref, sabs, what="large ragged batches n=136")
