@@ -26,6 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 FP64 flop/clk
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
 def bloch_flops_per_k(n: int, n_R: int, nR0: int, N0: int) -> float:
@@ -322,6 +323,14 @@ def measure_gf(reps: int = 3, n_fermi: int = 8, n_omega: int = 16, gamma: float 
             "sigma_checksum": float(sig.sum().item())}
 
 
+def big_reduction_bytes_per_k(n: int) -> int:
+    """HBM bytes per k-point the large-n Householder reduction has to move: at step k the
+    lower triangle (diagonal included) of rows/columns k+2.. is read and written once
+    (16-byte complex elements), and step 0 reads the whole matrix once."""
+    tri = sum(m * (m + 1) // 2 for m in range(1, n - 1))
+    return 16 * (2 * tri + n * n)
+
+
 def measure_large_n(reps: int = 3, n: int = 256, grid=(16, 16, 16), n_fermi: int = 16):
     """The large-n path (128 < n <= 512: many workgroups per k-point): a random n = 256 model
     on R in {-1..1}^3 (27 lattice vectors), a 16^3 grid, 16 Fermi levels over [-3, 3],
@@ -342,17 +351,31 @@ def measure_large_n(reps: int = 3, n: int = 256, grid=(16, 16, 16), n_fermi: int
     sig = torch.empty(1, n_fermi, dtype=torch.float64, device=dev)
     plan.forward(t, efd, 1e-3, 0.01, out=sig)
     torch.cuda.synchronize()
+    plan.kernel_time(4, reset=True)
     ms, alls = _timed_median(lambda: plan.forward(t, efd, 1e-3, 0.01, out=sig), reps, stream)
     st = plan.device_status()
     if st != kubo.KUBO_OK:
         raise SystemExit(f"large-n device status: {kubo.kubo_status_string(st)}")
     fpk = forward_flops_per_k(m.n, m.n_R, n_rx(m), grid[0], n_fermi, True)
+    # the reduction kernel (bound by HBM bandwidth): HIP events around each of its launches
+    red_ms, red_launches, red_k = plan.kernel_time(4)
+    bpk = big_reduction_bytes_per_k(n)
+    red_gbs = bpk * red_k / (red_ms / 1e3) / 1e9 if red_ms > 0 else None
     print(f"large n={n} {ms:.1f} ms", file=sys.stderr, flush=True)
     return {"workload": f"n{n}_R27_k16^3_F{n_fermi}_kT0.01", "k_points": nk, "reps": reps,
             "ms_median": ms, "ms_all": alls, "k_points_per_s": nk / (ms / 1e3),
             "flops_per_k": fpk,
             "tflops": fpk * nk / (ms / 1e3) / 1e12,
             "frac": fpk * nk / (ms / 1e3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
+            "reduction_roofline": {
+                "bound": "hbm", "kernel": "k_big_tridiag", "achieved": red_gbs,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": red_gbs / HBM_PEAK_GBS if red_gbs else None,
+                "bytes_per_k": bpk, "launches": red_launches,
+                "k_points_per_launch": red_k / red_launches if red_launches else None,
+                "ms_per_launch": red_ms / red_launches if red_launches else None,
+                "bytes_model": "lower triangle of the trailing matrix read and written once per step, "
+                               "the whole matrix read once at step 0"},
             "sigma_checksum": float(sig.sum().item())}
 
 

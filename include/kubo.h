@@ -232,7 +232,9 @@ const char* kubo_status_string(kubo_status status);
  * KUBO_F_TIMING since the last reset.  which = 0: the forward per-k kernel
  * (Bloch sum, eigensolve, rotation, curvature and Fermi sums); which = 1: the
  * backward per-k kernel; which = 2: the per-k kernel of kubo_ahc_tensor; which
- * = 3: the per-k kernel of kubo_ahc_gf.  Waits for the recorded events.  Outputs (each may
+ * = 3: the per-k kernel of kubo_ahc_gf; which = 4: the Householder reduction
+ * kernel of the large-n path alone (which = 0 covers its whole pipeline).  Waits
+ * for the recorded events.  Outputs (each may
  * be NULL): total_ms, the number of launches, and the k-points they covered.
  * reset != 0 forgets the records afterwards.  KUBO_E_INVALID for a NULL plan
  * or a bad which; KUBO_E_HIP if an event query fails.

@@ -850,7 +850,7 @@ static hipError_t gemm(int opa, int opb, const BigGemm& g, int items, hipStream_
     return hipGetLastError();
 }
 
-hipError_t launch_big_forward(const BigLaunch& L, hipStream_t s) {
+hipError_t launch_big_forward(const BigLaunch& L, hipStream_t s, hipEvent_t red_start, hipEvent_t red_stop) {
     if (L.count <= 0) return hipSuccess;
     if (L.n < 2 || L.n > kBigMaxN) return hipErrorInvalidValue;
     const int n = L.n;
@@ -862,11 +862,13 @@ hipError_t launch_big_forward(const BigLaunch& L, hipStream_t s) {
     hipLaunchKernelGGL(k_big_build, dim3((unsigned)((nn + 255) / 256 < 64 ? (nn + 255) / 256 : 64), L.count),
                        dim3(256), 0, s, L);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (red_start && (e = hipEventRecord(red_start, s)) != hipSuccess) return e;
     if (L.n <= 258)
         hipLaunchKernelGGL((k_big_tridiag<4, 2>), dim3(L.count), dim3(1024), 0, s, L);
     else
         hipLaunchKernelGGL((k_big_tridiag<8, 1>), dim3(L.count), dim3(1024), 0, s, L);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (red_stop && (e = hipEventRecord(red_stop, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_big_eig, dim3(L.count), dim3(kBigMaxN), 0, s, L);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_big_vec, dim3(L.count), dim3(kBigMaxN), 0, s, L);

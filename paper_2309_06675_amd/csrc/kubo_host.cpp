@@ -583,7 +583,10 @@ struct TimedScope {
     hipStream_t s;
     bool on = false;
     kubo_plan_s::TimeRec rec{};
-    TimedScope(kubo_plan_s* P_, hipStream_t s_, int which, long long kpts) : P(P_), s(s_) {
+    // record_now = false: the caller records start_event() and stop_event() itself
+    // (around one launch inside a pipeline) and files them with finish_recorded()
+    TimedScope(kubo_plan_s* P_, hipStream_t s_, int which, long long kpts, bool record_now = true)
+        : P(P_), s(s_) {
         if (!(P->flags & KUBO_F_TIMING) || P->capturing || P->no_events) return;
         if (P->tpool.empty()) {
             hipEvent_t a, b;
@@ -599,8 +602,15 @@ struct TimedScope {
         rec.start = P->tpool.back().first;
         rec.stop = P->tpool.back().second;
         P->tpool.pop_back();
-        on = hipEventRecord(rec.start, s) == hipSuccess;
+        on = !record_now || hipEventRecord(rec.start, s) == hipSuccess;
         if (!on) P->tpool.push_back({rec.start, rec.stop});
+    }
+    hipEvent_t start_event() const { return on ? rec.start : nullptr; }
+    hipEvent_t stop_event() const { return on ? rec.stop : nullptr; }
+    void finish_recorded() {
+        if (!on) return;
+        P->trec.push_back(rec);
+        on = false;
     }
     void finish() {
         if (!on) return;
@@ -664,7 +674,9 @@ kubo_status enqueue_forward(kubo_plan_s* P, const double* t, const double* ef, d
                     L.n = n;
                     L.item_begin = i;
                     L.count = j - i;
-                    HIP_TRY(launch_big_forward(L, s));
+                    TimedScope tr(P, s, 4, j - i, false);  // the reduction kernel alone
+                    HIP_TRY(launch_big_forward(L, s, tr.start_event(), tr.stop_event()));
+                    tr.finish_recorded();
                     i = j;
                 }
             } else if (kClasses[k].wave) {
@@ -991,7 +1003,7 @@ kubo_status kubo_plan_device_status(kubo_plan_t plan, const void* workspace, voi
 
 kubo_status kubo_plan_kernel_time(kubo_plan_t plan, int32_t which, double* total_ms,
                                   int64_t* launches, int64_t* k_points, int32_t reset) {
-    if (!plan || which < 0 || which > 3) return KUBO_E_INVALID;
+    if (!plan || which < 0 || which > 4) return KUBO_E_INVALID;
     double ms = 0.0;
     long long nl = 0, kp = 0;
     for (const auto& r : plan->trec) {

@@ -128,7 +128,9 @@ struct BigGemm {
     double alpha;
     int beta;
 };
-hipError_t launch_big_forward(const BigLaunch& L, hipStream_t s);
+// red_start / red_stop (null: none): events recorded around the reduction kernel
+hipError_t launch_big_forward(const BigLaunch& L, hipStream_t s, hipEvent_t red_start = nullptr,
+                              hipEvent_t red_stop = nullptr);
 
 long long wg_slot_elems(int nmax);
 // np: the size class (64: n <= 64, 128: n <= 128)

@@ -184,7 +184,8 @@ def kubo_plan_info(plan):
 
 
 def kubo_plan_kernel_time(plan, which: int, reset: bool = False):
-    """(status, total_ms, launches, k_points) of the per-k kernel `which` (0 fwd, 1 bwd)."""
+    """(status, total_ms, launches, k_points) of timing slot `which` (0 forward, 1 backward,
+    2 tensor, 3 Green's-function form, 4 the large-n reduction kernel)."""
     ms = ctypes.c_double()
     nl = ctypes.c_int64()
     kp = ctypes.c_int64()
@@ -380,7 +381,7 @@ class Plan:
 
     def kernel_time(self, which: int = 0, reset: bool = False):
         """(total_ms, launches, k_points) recorded under KUBO_F_TIMING (which: 0 forward,
-        1 backward, 2 tensor)."""
+        1 backward, 2 tensor, 3 Green's-function form, 4 the large-n reduction kernel)."""
         st, ms, nl, kp = kubo_plan_kernel_time(self.handle, which, reset)
         if st != KUBO_OK:
             raise KuboError(st, "kubo_plan_kernel_time")

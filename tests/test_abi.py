@@ -159,6 +159,20 @@ def test_plan_info_counts_slabs():
     kubo.kubo_plan_destroy(None)
 
 
+def test_kernel_time_slots():
+    """which = 0..4 are timing slots (4: the large-n reduction alone); a plan that ran
+    nothing reports zero launches without touching a device; other values are invalid."""
+    d, keep = _desc(n=200, grid=(3, 2, 2))
+    st, h, ws = kubo.kubo_plan([d], 1, kubo.KUBO_F_FORWARD_ONLY | kubo.KUBO_F_TIMING)
+    assert st == kubo.KUBO_OK
+    for which in range(5):
+        st, ms, nl, kp = kubo.kubo_plan_kernel_time(h, which)
+        assert st == kubo.KUBO_OK and (ms, nl, kp) == (0.0, 0, 0)
+    for which in (-1, 5):
+        assert kubo.kubo_plan_kernel_time(h, which)[0] == kubo.KUBO_E_INVALID
+    kubo.kubo_plan_destroy(h)
+
+
 def test_tensor_plan_sizes_and_argument_checks():
     """A KUBO_F_TENSOR plan needs room for a third set of partial Bloch sums and four
     result components; kubo_ahc_tensor on a plan without the flag is rejected before any
