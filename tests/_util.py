@@ -33,7 +33,8 @@ def workload_fermi(cfg: int, wl=None):
 
 
 # worst error/bound ratio of every parity comparison of the session; conftest
-# writes them to gpurun_out/parity_margins.json at the end of a GPU session
+# writes them to parity_margins.json in the folder KUBO_MARGINS_DIR names (if set)
+# at the end of the session
 MARGINS = []
 
 

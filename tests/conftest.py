@@ -28,9 +28,9 @@ def pytest_sessionfinish(session, exitstatus):
         from _util import MARGINS
     except ImportError:
         return
-    if not MARGINS:
+    out = os.environ.get("KUBO_MARGINS_DIR")
+    if not MARGINS or not out:
         return
-    out = os.path.join(ROOT, "gpurun_out")
     os.makedirs(out, exist_ok=True)
     with open(os.path.join(out, "parity_margins.json"), "w") as f:
         json.dump(MARGINS, f, indent=1)
