@@ -77,10 +77,14 @@ __global__ void k_hermproj(Tables tb, int n_models, long long total, const doubl
 
 // ---------------------------------------------------------------------------
 // k_pencil: per (model, i1, i2) the rho-resolved partial Bloch sums, for a group
-// of up to kPencilGroup pencils of one model at a time: each thread owns one
-// matrix element, reads each hopping t'(R) of it once and accumulates it into
-// every pencil of the group (the group's phases sit in LDS, a tile of lattice
-// vectors at a time).  Grid: x = pencil group, y = tile of 256 matrix elements.
+// of up to kPencilGroup pencils of one model and one k_z index (i2) at a time.
+// Each thread owns one matrix element.  The lattice vectors of an R_x group come
+// ordered by (R_y, R_z), so each run of equal R_y is first summed over R_z with
+// the group's common k_z phase, reading each hopping t'(R) once, and the run's sum
+// then goes into every pencil of the group with that pencil's k_y phase (the sum
+// over R factorised as sum over R_y of e^{i k_y R_y} sum over R_z).  Phases sit in
+// LDS, a tile of lattice vectors at a time.  Grid: x = pencil group, y = tile of
+// 256 matrix elements.
 // ---------------------------------------------------------------------------
 constexpr int kPencilThreads = 256;
 constexpr int kPencilPhaseTile = 256;
@@ -88,7 +92,8 @@ constexpr int kPencilPhaseTile = 256;
 __global__ __launch_bounds__(kPencilThreads) void k_pencil(Tables tb, int group_begin,
                                                            const double2* __restrict__ tp,
                                                            double2* __restrict__ tbuf, bool with_z) {
-    __shared__ double2 sph[kPencilPhaseTile][kPencilGroup];
+    __shared__ double2 sph[kPencilPhaseTile][kPencilGroup];  // e^{i k_y(q) R_y(g)}
+    __shared__ double2 sphz[kPencilPhaseTile];               // e^{i k_z R_z(g)}
     const PencilGroup grp = tb.pgroups[group_begin + blockIdx.x];
     const PencilItem p0 = tb.pencils[grp.first];
     const ModelDev md = tb.models[p0.model];
@@ -107,35 +112,50 @@ __global__ __launch_bounds__(kPencilThreads) void k_pencil(Tables tb, int group_
         for (int gt = g0; gt < g1; gt += kPencilPhaseTile) {
             const int gcount = min(kPencilPhaseTile, g1 - gt);
             __syncthreads();
-            for (int idx = threadIdx.x; idx < gcount * kPencilGroup; idx += kPencilThreads) {
-                const int g = idx / kPencilGroup, q = idx - g * kPencilGroup;
+            for (int idx = threadIdx.x; idx < gcount * (kPencilGroup + 1); idx += kPencilThreads) {
+                const int g = idx / (kPencilGroup + 1), q = idx - g * (kPencilGroup + 1);
                 const int gi = md.grp_first + gt + g;
-                double2 ph = c_make(0.0, 0.0);
-                if (q < cnt) {
-                    const PencilItem pi = tb.pencils[grp.first + q];
-                    ph = unit_phase2((long long)pi.i1 * tb.grp_R1[gi], md.N1,
-                                     (long long)pi.i2 * tb.grp_R2[gi], md.N2);
+                if (q == kPencilGroup) {
+                    sphz[g] = unit_phase((long long)p0.i2 * tb.grp_R2[gi], md.N2);
+                } else {
+                    double2 ph = c_make(0.0, 0.0);
+                    if (q < cnt) ph = unit_phase((long long)tb.pencils[grp.first + q].i1 * tb.grp_R1[gi], md.N1);
+                    sph[g][q] = ph;
                 }
-                sph[g][q] = ph;
             }
             __syncthreads();
             if (act) {
-                for (int g = 0; g < gcount; ++g) {
-                    const int gi = md.grp_first + gt + g;
-                    const int r = tb.grp_r[gi];
-                    const double ry = (double)tb.grp_R1[gi], rz = (double)tb.grp_R2[gi];
-                    const double2 v = tp[md.t_off + (long long)r * nn + e];
-                    const double2 vy = c_i(c_scale(ry, v)), vz = c_i(c_scale(rz, v));
+                // the current run of equal R_y: its R_z sums (u; uz for v_z) and the tile
+                // index of its first lattice vector (whose k_y phases the run takes)
+                double2 u = c_make(0.0, 0.0), uz = u;
+                int run_g = -1, run_ry = 0;
+                auto flush = [&]() {
+                    const double2 uy = c_i(c_scale((double)run_ry, u));
 #pragma unroll
                     for (int q = 0; q < kPencilGroup; ++q) {
                         if (q < cnt) {
-                            const double2 ph = sph[g][q];
-                            a0[q] = c_fma(v, ph, a0[q]);
-                            a1[q] = c_fma(vy, ph, a1[q]);
-                            if (with_z) a2[q] = c_fma(vz, ph, a2[q]);
+                            const double2 py = sph[run_g][q];
+                            a0[q] = c_fma(u, py, a0[q]);
+                            a1[q] = c_fma(uy, py, a1[q]);
+                            if (with_z) a2[q] = c_fma(uz, py, a2[q]);
                         }
                     }
+                };
+                for (int g = 0; g < gcount; ++g) {
+                    const int gi = md.grp_first + gt + g;
+                    const int ry = tb.grp_R1[gi];
+                    if (run_g < 0 || ry != run_ry) {
+                        if (run_g >= 0) flush();
+                        u = uz = c_make(0.0, 0.0);
+                        run_g = g;
+                        run_ry = ry;
+                    }
+                    const double2 v = tp[md.t_off + (long long)tb.grp_r[gi] * nn + e];
+                    const double2 pz = sphz[g];
+                    u = c_fma(v, pz, u);
+                    if (with_z) uz = c_fma(c_i(c_scale((double)tb.grp_R2[gi], v)), pz, uz);
                 }
+                if (run_g >= 0) flush();  // a run that goes on in the next tile restarts there
             }
         }
         if (act) {

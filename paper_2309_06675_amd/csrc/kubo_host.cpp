@@ -225,14 +225,22 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
         for (int xi = 0; xi < (int)xs.size(); ++xi) {
             const int acc0 = acc;
             P->grp_start.push_back(acc);
+            // the group's lattice vectors ordered by (R_y, R_z): the pencil sums take
+            // each run of equal R_y as one R_z sum
+            std::vector<int> rs;
             for (int r = 0; r < d.n_R; ++r)
-                if (d.R[3 * r] == xs[xi]) {
-                    P->grp_r.push_back(r);
-                    P->grp_R1.push_back(d.R[3 * r + 1]);
-                    P->grp_R2.push_back(d.R[3 * r + 2]);
-                    P->grp_rho.push_back(xi);
-                    ++acc;
-                }
+                if (d.R[3 * r] == xs[xi]) rs.push_back(r);
+            std::stable_sort(rs.begin(), rs.end(), [&](int u, int v) {
+                return std::make_pair(d.R[3 * u + 1], d.R[3 * u + 2]) <
+                       std::make_pair(d.R[3 * v + 1], d.R[3 * v + 2]);
+            });
+            for (int r : rs) {
+                P->grp_r.push_back(r);
+                P->grp_R1.push_back(d.R[3 * r + 1]);
+                P->grp_R2.push_back(d.R[3 * r + 2]);
+                P->grp_rho.push_back(xi);
+                ++acc;
+            }
             P->max_group = std::max(P->max_group, acc - acc0);
         }
         P->max_nR = std::max(P->max_nR, d.n_R);
@@ -327,12 +335,12 @@ kubo_status build_plan(kubo_plan_s* P, const kubo_model_desc* models, int n_mode
         std::vector<std::vector<BlockItem>> cls_blocks(kNumClasses);
         auto flush = [&]() {
             if (cur.pencil_count == 0) return;
-            // pencil groups: runs of one model, at most kPencilGroup long
+            // pencil groups: runs of one model and one k_z index, at most kPencilGroup long
             cur.pgroup_begin = (int)cs.pgroups.size();
             for (int p = cur.pencil_begin; p < cur.pencil_begin + cur.pencil_count;) {
                 int q = p + 1;
                 while (q < cur.pencil_begin + cur.pencil_count && q - p < kPencilGroup &&
-                       cs.pencils[q].model == cs.pencils[p].model)
+                       cs.pencils[q].model == cs.pencils[p].model && cs.pencils[q].i2 == cs.pencils[p].i2)
                     ++q;
                 cs.pgroups.push_back(PencilGroup{p, q - p});
                 p = q;
